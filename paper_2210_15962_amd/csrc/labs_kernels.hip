@@ -1,0 +1,812 @@
+// labs_kernels.hip -- gfx950 kernels of liblabs.so.
+//
+// Self-avoiding walks over skew-symmetric binary sequences (Boskovic, Herzog
+// & Brest, arXiv 2210.15962, Sec. 3, Eq. 2-4, Alg. 2), scored with an exact
+// integer neighbour evaluation written for the CDNA4 vector ALUs.
+//
+// Notation: L odd, D = (L+1)/2 free bits, m = (L-1)/2 even lags k = 2t+2
+// (t = 0..m-1).  On a skew-symmetric sequence every odd-lag C_k is zero, and
+// negating free bit j (j < D) flips sequence positions j and L+1-j (j = D
+// flips the centre only).  Writing s for the sequence, C_t for the even-lag
+// autocorrelations and u_t for the change of C_t divided by 4, the move's
+// energy change is
+//     dE_j = 8 * sum_t u_t C_t + 16 * sum_t u_t^2,
+//     u_t  = -s_j (MF_t s_{j+k} + MB_t s_{j-k}),
+// where MF selects forward lags that stay inside the sequence (minus the lag
+// k0 = L+1-2j, whose pair (j, L+1-j) keeps its product) and MB the backward
+// lags.  (Derived from Eq. 1 and Eq. 2.)
+//
+// Data layout per walk (replicated in each of the lanes cooperating on it):
+//   * sequence: four bit arrays in the lane's LDS column -- odd and even
+//     sequence positions, each forwards and reversed, so the forward and
+//     backward neighbours of any j are one funnel shift away;
+//   * C: two's-complement bit planes of c_t = (C_t - 1)/2 in VGPRs, 32 lags
+//     per word; sum_t s_t C_t over a mask M is 2 * sum_M (c_t XOR -f_t) + |M|
+//     (f_t = 1 where s_t = -1), i.e. XOR, AND and popcount per plane word;
+//   * visited set: exact open-addressing table in HBM keyed on the packed
+//     free bits (64-byte buckets, linear probing, no deletions).
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <type_traits>
+#include "labs_internal.h"
+
+namespace lsaw {
+
+template <int I, int N, class F>
+__device__ __forceinline__ void static_for(F &&f) {
+  if constexpr (I < N) {
+    f(std::integral_constant<int, I>{});
+    static_for<I + 1, N>(f);
+  }
+}
+
+// v[i] for a small register array and a runtime index (select chain, no scratch).
+template <int N>
+__device__ __forceinline__ uint32_t sel(const uint32_t (&v)[N], int i) {
+  uint32_t r = v[0];
+#pragma unroll
+  for (int k = 1; k < N; ++k) r = (i == k) ? v[k] : r;
+  return r;
+}
+
+// ---------------------------------------------------------------------------
+// Small helpers
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint64_t mix64(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+__device__ __forceinline__ uint32_t popc_add(uint32_t x, uint32_t acc) {
+  return (uint32_t)__builtin_popcount(x) + acc;
+}
+
+__device__ __forceinline__ uint32_t funnel(uint32_t hi, uint32_t lo, uint32_t sh) {
+  return __builtin_amdgcn_alignbit(hi, lo, sh);
+}
+
+// Min / max over the G consecutive lanes that cooperate on one walk.
+template <int G>
+__device__ __forceinline__ uint32_t group_min(uint32_t v) {
+  if constexpr (G >= 2) v = min(v, (uint32_t)__builtin_amdgcn_ds_swizzle((int)v, 0x041F));
+  if constexpr (G >= 4) v = min(v, (uint32_t)__builtin_amdgcn_ds_swizzle((int)v, 0x081F));
+  if constexpr (G >= 8) v = min(v, (uint32_t)__builtin_amdgcn_ds_swizzle((int)v, 0x101F));
+  return v;
+}
+template <int G>
+__device__ __forceinline__ uint32_t group_max(uint32_t v) {
+  if constexpr (G >= 2) v = max(v, (uint32_t)__builtin_amdgcn_ds_swizzle((int)v, 0x041F));
+  if constexpr (G >= 4) v = max(v, (uint32_t)__builtin_amdgcn_ds_swizzle((int)v, 0x081F));
+  if constexpr (G >= 8) v = max(v, (uint32_t)__builtin_amdgcn_ds_swizzle((int)v, 0x101F));
+  return v;
+}
+
+// ---------------------------------------------------------------------------
+// Geometry of one lag-word class NW (L with ceil(m/32) == NW)
+// ---------------------------------------------------------------------------
+__host__ __device__ constexpr int lmax_of(int nw) { return (64 * nw + 1) < kLMax ? (64 * nw + 1) : kLMax; }
+__host__ __device__ constexpr int clog2(int v) { int b = 0; while ((1 << b) < v) ++b; return b; }
+// Planes of word w: |c_t| <= (L - 64w - 1)/2 for lags of that word, and
+// two's complement with B bits holds [-2^(B-1), 2^(B-1)-1].
+__host__ __device__ constexpr int planes_of(int nw, int w) {
+  return 1 + clog2((lmax_of(nw) - 64 * w - 1) / 2);
+}
+__host__ __device__ constexpr int plane_off(int nw, int w) {
+  int s = 0;
+  for (int i = 0; i < w; ++i) s += planes_of(nw, i);
+  return s;
+}
+
+template <int NW>
+struct Geom {
+  static constexpr int NWB = (NW + 1) / 2;           // backward lag words
+  static constexpr int NWA = NW + NWB + 1;           // words per bit array
+  static constexpr int DMAX = (32 * NW + 1) < 192 ? (32 * NW + 1) : 192;
+  static constexpr int DESC = ((9 + NW + 2 * NWB) + 3) & ~3;  // dwords per row
+  static constexpr int NPW = plane_off(NW, NW);      // plane words in total
+  static constexpr int BMAX = planes_of(NW, 0);
+  static constexpr size_t lds_bytes() {
+    return (size_t)DMAX * DESC * 4 + (size_t)4 * NWA * kBlock * 4;
+  }
+};
+
+// Descriptor row of candidate j (dword offsets).
+enum : int {
+  DS_FOFF = 0,   // byte offset (within a lane column) of forward source word 0
+  DS_FSH = 1,    // funnel shift of the forward vector
+  DS_BOFF = 2,
+  DS_BSH = 3,
+  DS_SOFF = 4,   // byte offset of the word holding s_j
+  DS_SPOS = 5,   // bit position of s_j in that word
+  DS_KC = 6,     // 2N + 4|MF & MB| + kBias
+  DS_N = 7,      // |MF| + |MB|
+  DS_JM1 = 8,    // j - 1
+  DS_MASKS = 9   // MF[NW], MB[NWB], MFB[NWB]
+};
+
+constexpr uint32_t kKeyMax = 0xFFFFFFFFu;
+constexpr int32_t kBias = 1 << 23;      // dE/8 bias inside a candidate key
+
+// Column layout: array a (0: odd positions forward, 1: even forward,
+// 2: odd reversed, 3: even reversed), word w, lane l -> dword
+// ((a*NWA + w) * kBlock + l).  Consecutive lanes hit consecutive banks.
+template <int NW>
+__device__ __forceinline__ uint32_t col_word_off(int a, int w) {
+  return (uint32_t)(((a * Geom<NW>::NWA + w) * kBlock) * 4);
+}
+
+__device__ __forceinline__ uint32_t prefix_mask(int n, int w) {
+  const int len = n - 32 * w;
+  return len >= 32 ? 0xFFFFFFFFu : (len <= 0 ? 0u : ((1u << len) - 1u));
+}
+
+template <int NW>
+__device__ __forceinline__ void build_descriptors(uint32_t *desc, int L) {
+  using Gm = Geom<NW>;
+  const int D = (L + 1) / 2, m = (L - 1) / 2;
+#pragma unroll 1
+  for (int j = 1 + (int)threadIdx.x; j <= D; j += blockDim.x) {
+    uint32_t *row = desc + (j - 1) * Gm::DESC;
+    const int c = j & 1;                         // class: 1 odd positions, 0 even
+    const int n_c = c ? D : m;                   // class size
+    const int r = (j - 1) >> 1;                  // index of s_j in its class
+    const int afwd = c ? 0 : 1, arev = afwd + 2;
+    const int fstart = r + 1, bstart = n_c - r;
+    row[DS_FOFF] = col_word_off<NW>(afwd, fstart >> 5);
+    row[DS_FSH] = (uint32_t)(fstart & 31);
+    row[DS_BOFF] = col_word_off<NW>(arev, bstart >> 5);
+    row[DS_BSH] = (uint32_t)(bstart & 31);
+    row[DS_SOFF] = col_word_off<NW>(afwd, r >> 5);
+    row[DS_SPOS] = (uint32_t)(r & 31);
+    const int nF = (j < D) ? n_c - 1 - r : 0;    // forward lags inside [1, L]
+    const int nB = r;                            // backward lags inside [1, L]
+    const int hole = (j < D) ? D - 1 - j : -1;   // lag index of k0 = L+1-2j
+    int cntF = 0, cntB = 0, cntFB = 0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+      uint32_t mf = prefix_mask(nF, w);
+      if (hole >= 32 * w && hole < 32 * w + 32) mf &= ~(1u << (hole - 32 * w));
+      row[DS_MASKS + w] = mf;
+      cntF += __builtin_popcount(mf);
+      if (w < Gm::NWB) {
+        const uint32_t mb = prefix_mask(nB, w);
+        const uint32_t mfb = mb & mf;
+        row[DS_MASKS + NW + w] = mb;
+        row[DS_MASKS + NW + Gm::NWB + w] = mfb;
+        cntB += __builtin_popcount(mb);
+        cntFB += __builtin_popcount(mfb);
+      }
+    }
+    const int N = cntF + cntB;
+    row[DS_KC] = (uint32_t)(2 * N + 4 * cntFB + kBias);
+    row[DS_N] = (uint32_t)N;
+    row[DS_JM1] = (uint32_t)(j - 1);
+#pragma unroll
+    for (int i = DS_MASKS + NW + 2 * Gm::NWB; i < Gm::DESC; ++i) row[i] = 0;
+  }
+}
+
+// Forward / backward neighbour bit vectors of candidate j, its masks and s_j.
+template <int NW>
+struct CandVec {
+  uint32_t fw[NW];
+  uint32_t bw[Geom<NW>::NWB];
+  uint32_t mf[NW];
+  uint32_t mb[Geom<NW>::NWB];
+  uint32_t mfb[Geom<NW>::NWB];
+  uint32_t sbit;
+  int32_t kc, N;
+  uint32_t jm1;
+};
+
+template <int NW>
+__device__ __forceinline__ void load_candidate(const uint32_t *desc_row, const uint8_t *lds,
+                                               uint32_t colbase, CandVec<NW> &cv) {
+  using Gm = Geom<NW>;
+  const uint4 d0 = *reinterpret_cast<const uint4 *>(desc_row);
+  const uint4 d1 = *reinterpret_cast<const uint4 *>(desc_row + 4);
+  cv.kc = (int32_t)d1.z;
+  cv.N = (int32_t)d1.w;
+  cv.jm1 = desc_row[DS_JM1];
+#pragma unroll
+  for (int w = 0; w < NW; ++w) cv.mf[w] = desc_row[DS_MASKS + w];
+#pragma unroll
+  for (int w = 0; w < Gm::NWB; ++w) {
+    cv.mb[w] = desc_row[DS_MASKS + NW + w];
+    cv.mfb[w] = desc_row[DS_MASKS + NW + Gm::NWB + w];
+  }
+  const uint32_t *fsrc = reinterpret_cast<const uint32_t *>(lds + colbase + d0.x);
+  const uint32_t *bsrc = reinterpret_cast<const uint32_t *>(lds + colbase + d0.z);
+  uint32_t fs[NW + 1], bs[Gm::NWB + 1];
+#pragma unroll
+  for (int w = 0; w <= NW; ++w) fs[w] = fsrc[w * kBlock];
+#pragma unroll
+  for (int w = 0; w <= Gm::NWB; ++w) bs[w] = bsrc[w * kBlock];
+  const uint32_t sw = *reinterpret_cast<const uint32_t *>(lds + colbase + d1.x);
+#pragma unroll
+  for (int w = 0; w < NW; ++w) cv.fw[w] = funnel(fs[w + 1], fs[w], d0.y);
+#pragma unroll
+  for (int w = 0; w < Gm::NWB; ++w) cv.bw[w] = funnel(bs[w + 1], bs[w], d0.w);
+  cv.sbit = (sw >> d1.y) & 1u;
+}
+
+// Candidate key: ((dE/8 + kBias) << 8) | (j-1).  Unsigned order = (dE, j) order.
+template <int NW>
+__device__ __forceinline__ uint32_t candidate_key(const CandVec<NW> &cv, const uint32_t *P) {
+  using Gm = Geom<NW>;
+  constexpr int BM = Gm::BMAX;
+  uint32_t cnt[BM - 1];
+#pragma unroll
+  for (int b = 0; b < BM - 1; ++b) cnt[b] = 0;
+  int32_t X = 0;
+  static_for<0, NW>([&](auto wc) {
+    constexpr int w = decltype(wc)::value;
+    constexpr int Bw = planes_of(NW, w), off = plane_off(NW, w);
+    uint32_t s = 0;
+#pragma unroll
+    for (int b = 0; b < Bw - 1; ++b) cnt[b] = popc_add((P[off + b] ^ cv.fw[w]) & cv.mf[w], cnt[b]);
+    s = popc_add((P[off + Bw - 1] ^ cv.fw[w]) & cv.mf[w], s);
+    if constexpr (w < Gm::NWB) {
+#pragma unroll
+      for (int b = 0; b < Bw - 1; ++b) cnt[b] = popc_add((P[off + b] ^ cv.bw[w]) & cv.mb[w], cnt[b]);
+      s = popc_add((P[off + Bw - 1] ^ cv.bw[w]) & cv.mb[w], s);
+    }
+    X -= (int32_t)(s << (Bw - 1));   // sign plane of this word
+  });
+  // X += sum_b 2^b cnt_b  (Horner), giving sum over masked lags of (c_t XOR -f_t).
+  int32_t Hn = (int32_t)cnt[BM - 2];
+#pragma unroll
+  for (int b = BM - 3; b >= 0; --b) Hn = 2 * Hn + (int32_t)cnt[b];
+  X += Hn;
+  uint32_t q = 0;
+#pragma unroll
+  for (int w = 0; w < Gm::NWB; ++w) q = popc_add((cv.fw[w] ^ cv.bw[w]) & cv.mfb[w], q);
+  const int32_t Y = 2 * X + cv.N;
+  const int32_t Z = cv.kc - 8 * (int32_t)q;
+  const int32_t val = cv.sbit ? Z + Y : Z - Y;
+  return ((uint32_t)val << 8) | cv.jm1;
+}
+
+// c_t += 2u_t on the bit planes for the move j (u from the pre-move vectors):
+// u_t = -s_j * (a_t + b_t), a_t = MF_t ? (f_t ? -1 : 1) : 0, b_t likewise.
+template <int NW>
+__device__ __forceinline__ void apply_move_planes(const CandVec<NW> &cv, uint32_t *P) {
+  using Gm = Geom<NW>;
+  // s_j = +1 -> add -w = ~w + 1; s_j = -1 -> add w.
+  const uint32_t ms = cv.sbit ? 0u : 0xFFFFFFFFu;
+  static_for<0, NW>([&](auto wc) {
+    constexpr int w = decltype(wc)::value;
+    constexpr int Bw = planes_of(NW, w), off = plane_off(NW, w);
+    const uint32_t a0 = cv.mf[w], a1 = cv.fw[w] & cv.mf[w];
+    uint32_t b0 = 0u, b1 = 0u;
+    if constexpr (w < Gm::NWB) { b0 = cv.mb[w]; b1 = cv.bw[w] & b0; }
+    // w = a + b as 3-bit two's complement (bit 2 is the sign).
+    const uint32_t w0 = a0 ^ b0, c1 = a0 & b0;
+    const uint32_t t1 = a1 ^ b1;
+    const uint32_t w1 = t1 ^ c1;
+    const uint32_t c2 = (t1 & c1) | (a1 & b1);
+    const uint32_t w2 = t1 ^ c2;
+    const uint32_t u0 = w0 ^ ms, u1 = w1 ^ ms, u2 = w2 ^ ms;
+    uint32_t carry = ms;
+#pragma unroll
+    for (int b = 1; b < Bw; ++b) {
+      const uint32_t x = (b == 1) ? u0 : (b == 2) ? u1 : u2;
+      const uint32_t p = P[off + b];
+      const uint32_t t = p ^ x;
+      P[off + b] = t ^ carry;
+      carry = (t & carry) | (p & x);
+    }
+  });
+}
+
+// ---------------------------------------------------------------------------
+// Visited table
+// ---------------------------------------------------------------------------
+struct Key3 { uint64_t w0, w1, w2; };
+
+__device__ __forceinline__ uint32_t bucket_of(const Key3 &k, uint32_t n_buckets) {
+  uint64_t h = k.w0 * 0x9E3779B97F4A7C15ull ^ k.w1 * 0xC2B2AE3D27D4EB4Full ^
+               k.w2 * 0x165667B19E3779F9ull;
+  h = mix64(h);
+  return (uint32_t)(((h >> 32) * (uint64_t)n_buckets) >> 32);
+}
+
+// Scan one bucket.  Returns 2 = key present, 1 = absent (slot = first free
+// entry), 0 = bucket full without the key.
+__device__ __forceinline__ int scan_bucket(const uint8_t *bucket, const Key3 &k, bool e32,
+                                           uint32_t &slot) {
+  const uint4 *q = reinterpret_cast<const uint4 *>(bucket);
+  uint4 v0 = q[0], v1 = q[1], v2 = q[2], v3 = q[3];
+  const uint32_t k0l = (uint32_t)k.w0, k0h = (uint32_t)(k.w0 >> 32);
+  const uint32_t k1l = (uint32_t)k.w1, k1h = (uint32_t)(k.w1 >> 32);
+  if (!e32) {
+    uint4 e[4] = {v0, v1, v2, v3};
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const bool occ = (e[i].w >> 31) != 0;
+      if (!occ) { slot = (uint32_t)i * 16u; return 1; }
+      if (e[i].x == k0l && e[i].y == k0h && e[i].z == k1l && (e[i].w & 0x7FFFFFFFu) == k1h) return 2;
+    }
+    return 0;
+  } else {
+    const uint32_t k2l = (uint32_t)k.w2, k2h = (uint32_t)(k.w2 >> 32);
+    uint4 lo[2] = {v0, v2}, hi[2] = {v1, v3};
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const bool occ = hi[i].z != 0;
+      if (!occ) { slot = (uint32_t)i * 32u; return 1; }
+      if (lo[i].x == k0l && lo[i].y == k0h && lo[i].z == k1l && lo[i].w == k1h &&
+          hi[i].x == k2l && hi[i].y == k2h) return 2;
+    }
+    return 0;
+  }
+}
+
+__device__ __forceinline__ void store_entry(uint8_t *p, const Key3 &k, bool e32) {
+  if (!e32) {
+    uint4 v;
+    v.x = (uint32_t)k.w0; v.y = (uint32_t)(k.w0 >> 32);
+    v.z = (uint32_t)k.w1; v.w = (uint32_t)(k.w1 >> 32) | 0x80000000u;
+    *reinterpret_cast<uint4 *>(p) = v;
+  } else {
+    uint4 a, b;
+    a.x = (uint32_t)k.w0; a.y = (uint32_t)(k.w0 >> 32);
+    a.z = (uint32_t)k.w1; a.w = (uint32_t)(k.w1 >> 32);
+    b.x = (uint32_t)k.w2; b.y = (uint32_t)(k.w2 >> 32); b.z = 1u; b.w = 0u;
+    reinterpret_cast<uint4 *>(p)[0] = a;
+    reinterpret_cast<uint4 *>(p)[1] = b;
+  }
+}
+
+__device__ __forceinline__ Key3 flip_key(const Key3 &k, uint32_t jm1) {
+  Key3 r = k;
+  const uint64_t bit = 1ull << (jm1 & 63u);
+  const uint32_t w = jm1 >> 6;
+  r.w0 ^= (w == 0) ? bit : 0ull;
+  r.w1 ^= (w == 1) ? bit : 0ull;
+  r.w2 ^= (w == 2) ? bit : 0ull;
+  return r;
+}
+
+__device__ __forceinline__ uint32_t key_bit(const Key3 &k, int jm1) {
+  const uint64_t w = (jm1 >> 6) == 0 ? k.w0 : (jm1 >> 6) == 1 ? k.w1 : k.w2;
+  return (uint32_t)((w >> (jm1 & 63)) & 1ull);
+}
+
+// ---------------------------------------------------------------------------
+// Walk kernel
+// ---------------------------------------------------------------------------
+template <int K>
+__device__ __forceinline__ void topk_insert(uint32_t (&tk)[K], uint32_t x) {
+  if constexpr (K == 1) {
+    tk[0] = min(tk[0], x);
+  } else {
+    // Sorted insertion: new[i] = median(old[i-1], old[i], x), new[0] = min.
+#pragma unroll
+    for (int i = K - 1; i >= 1; --i) tk[i] = max(tk[i - 1], min(tk[i], x));  // tk sorted: median
+    tk[0] = min(tk[0], x);
+  }
+}
+
+template <int NW, int G, int K>
+__global__ void __launch_bounds__(kBlock) walk_kernel(const WalkLaunch a) {
+  using Gm = Geom<NW>;
+  extern __shared__ __align__(16) uint8_t lds[];
+  uint32_t *desc = reinterpret_cast<uint32_t *>(lds);
+  uint8_t *cols = lds + (size_t)Gm::DMAX * Gm::DESC * 4;
+
+  const int L = a.L, D = (L + 1) / 2, m = (L - 1) / 2;
+  const int KW = (D + 63) / 64;
+  build_descriptors<NW>(desc, L);
+  __syncthreads();
+
+  const int tid = (int)threadIdx.x;
+  const int r = tid % G;                       // lane rank inside the walk group
+  const int64_t local = (int64_t)blockIdx.x * (kBlock / G) + tid / G;
+  const int64_t walk = a.walk_begin + local;
+  bool active = local < a.n_walks;
+  const uint32_t colbase = (uint32_t)tid * 4u;
+  uint32_t *colw = reinterpret_cast<uint32_t *>(cols);
+  const bool e32 = D > 127;
+
+  // ---- first pivot P_1 ---------------------------------------------------
+  Key3 P{0, 0, 0};
+  if (active) {
+    auto start_word = [&](int t) -> uint64_t {
+      if (t >= KW) return 0ull;
+      uint64_t v;
+      if (a.starts) {
+        v = a.starts[walk * KW + t];
+      } else {
+        v = mix64(a.seed + 0x9E3779B97F4A7C15ull * ((uint64_t)walk * (uint64_t)KW + (uint64_t)t + 1u));
+      }
+      const int bits = D - 64 * t;
+      if (bits < 64) v &= ((1ull << bits) - 1ull);
+      return v;
+    };
+    P.w0 = start_word(0);
+    P.w1 = start_word(1);
+    P.w2 = start_word(2);
+  }
+
+  // ---- sequence bit arrays (Eq. 2 expansion) -------------------------------
+  for (int i = 0; i < 4 * Gm::NWA; ++i) colw[i * kBlock + tid] = 0u;
+  const int n1 = D, n0 = m;
+#pragma unroll 1
+  for (int i = 1; i <= L; ++i) {
+    uint32_t bit;
+    if (i <= D) bit = key_bit(P, i - 1);
+    else bit = key_bit(P, L - i) ^ (uint32_t)((i - D) & 1);   // s_{D+k} = (-1)^k s_{D-k}
+    if (bit) {
+      const int c = i & 1, rr = (i - 1) >> 1, nc = c ? n1 : n0;
+      const int af = c ? 0 : 1;
+      colw[(af * Gm::NWA + (rr >> 5)) * kBlock + tid] |= 1u << (rr & 31);
+      const int rv = nc - 1 - rr;
+      colw[((af + 2) * Gm::NWA + (rv >> 5)) * kBlock + tid] |= 1u << (rv & 31);
+    }
+  }
+
+  // ---- C_t (even lags) -> planes of c_t = (C_t - 1)/2, and E(P_1) --------------
+  uint32_t Pl[Gm::NPW];
+#pragma unroll
+  for (int i = 0; i < Gm::NPW; ++i) Pl[i] = 0u;
+  int32_t E = 0;
+  static_for<0, NW>([&](auto wc) {
+    constexpr int w = decltype(wc)::value;
+    constexpr int Bw = planes_of(NW, w), off = plane_off(NW, w);
+#pragma unroll 1
+    for (int tb = 0; tb < 32; ++tb) {
+      const int t = 32 * w + tb;
+      if (t >= m) break;
+      const int sh = t + 1;                    // class distance of lag k = 2t+2
+      int mism = 0;
+      for (int c = 0; c < 2; ++c) {
+        const int nc = c ? n1 : n0, af = c ? 0 : 1;
+        const int npairs = nc - sh;
+        for (int ww = 0; 32 * ww < npairs; ++ww) {
+          const uint32_t x = colw[(af * Gm::NWA + ww) * kBlock + tid];
+          const int q = ww + (sh >> 5);
+          const uint32_t lo = colw[(af * Gm::NWA + q) * kBlock + tid];
+          const uint32_t hi = (q + 1 < Gm::NWA) ? colw[(af * Gm::NWA + q + 1) * kBlock + tid] : 0u;
+          const uint32_t y = funnel(hi, lo, (uint32_t)(sh & 31));
+          const int rem = npairs - 32 * ww;
+          const uint32_t msk = rem >= 32 ? 0xFFFFFFFFu : ((1u << rem) - 1u);
+          mism += __builtin_popcount((x ^ y) & msk);
+        }
+      }
+      const int32_t Ct = (L - 2 * t - 2) - 2 * mism;
+      E += Ct * Ct;
+      const int32_t ct = (Ct - 1) >> 1;
+#pragma unroll
+      for (int b = 0; b < Bw; ++b) Pl[off + b] |= (uint32_t)((ct >> b) & 1) << tb;
+    }
+  });
+
+  int32_t bestE = E;
+  Key3 bestP = P;
+  uint64_t h = 0;
+  int64_t steps = 0;
+  uint32_t prev_jm1 = 0xFFFFFFFFu;
+  uint8_t *table = a.tables + (uint64_t)(active ? local : 0) * a.table_bytes;
+
+  // Insert P_1 (the table is empty: first entry of its home bucket).
+  if (active && r == 0) store_entry(table + (uint64_t)bucket_of(P, a.n_buckets) * kBucketBytes, P, e32);
+
+  // Local candidates of lane r: j = r + 1 + G*i.
+  const int ncand = (D - r + G - 1) / G;       // may be 0 for r >= D
+  const bool tracing = active && walk < a.n_trace;
+
+  for (int64_t step = 0; step < a.walk_len; ++step) {
+    if (__ballot(active) == 0ull) break;
+    // Excluded local candidates (bit i <-> j = r + 1 + G*i): the predecessor,
+    // then every candidate found visited during this step.
+    uint64_t ex0 = 0ull, ex1 = 0ull, ex2 = 0ull;
+    auto exclude = [&](uint32_t li) {
+      const uint64_t bit = 1ull << (li & 63u);
+      const uint32_t q = li >> 6;
+      ex0 |= (q == 0u) ? bit : 0ull;
+      ex1 |= (q == 1u) ? bit : 0ull;
+      ex2 |= (q == 2u) ? bit : 0ull;
+    };
+    if (prev_jm1 != 0xFFFFFFFFu && (int)(prev_jm1 % G) == r) exclude(prev_jm1 / G);
+
+    uint32_t tk[K];
+    bool lane_empty = false;      // no non-excluded local candidate is left
+    int npop = 0;                 // entries popped from tk (head is tk[0])
+    int hstat = 0;                // head: 0 unknown, 1 absent, 2 visited
+    bool pstarted = false;
+    uint32_t pbucket = 0, pslot = 0;
+    Key3 pkey{0, 0, 0};
+    bool need_scan = true;
+    bool done = !active;
+    uint32_t win = kKeyMax;
+
+    for (;;) {
+      // (1) scan / rescan of local candidates, skipping excluded ones.
+      if (__ballot(!done && need_scan) != 0ull) {
+        if (!done && need_scan) {
+#pragma unroll
+          for (int i = 0; i < K; ++i) tk[i] = kKeyMax;
+        }
+        const int nmax = (D + G - 1) / G;
+        uint64_t xw = 0ull;
+#pragma unroll 1
+        for (int i = 0; i < nmax; ++i) {
+          if ((i & 63) == 0) xw = (i < 64) ? ex0 : (i < 128) ? ex1 : ex2;
+          const bool live = !done && need_scan && i < ncand;
+          const int j = live ? (r + 1 + G * i) : 1;
+          CandVec<NW> cv;
+          load_candidate<NW>(desc + (j - 1) * Gm::DESC, cols, colbase, cv);
+          uint32_t key = candidate_key<NW>(cv, Pl);
+          key |= 0u - (uint32_t)(xw & 1ull);
+          xw >>= 1;
+          if (live) topk_insert<K>(tk, key);
+        }
+        if (!done && need_scan) {
+          need_scan = false;
+          npop = 0;
+          hstat = 0;
+          pstarted = false;
+          lane_empty = tk[0] == kKeyMax;
+        }
+      }
+      // (2) probe the head of every lane whose head status is unknown.
+      const uint32_t head = tk[0];
+      const bool head_valid = !done && !lane_empty && npop < K && head != kKeyMax;
+      if (head_valid && hstat == 0) {
+        const uint32_t hk = head;
+        if (!pstarted) {
+          pkey = flip_key(P, hk & 0xFFu);
+          pbucket = bucket_of(pkey, a.n_buckets);
+          pstarted = true;
+        }
+        uint32_t slot = 0;
+        const int res = scan_bucket(table + (uint64_t)pbucket * kBucketBytes, pkey, e32, slot);
+        if (res == 2) {
+          hstat = 2;
+        } else if (res == 1) {
+          hstat = 1;
+          pslot = pbucket * (uint32_t)kBucketBytes + slot;
+        } else {
+          pbucket = (pbucket + 1u == a.n_buckets) ? 0u : pbucket + 1u;
+        }
+      }
+      // (3) merge the heads of the group.
+      const uint32_t my = head_valid ? head : kKeyMax;
+      const uint32_t gmin = group_min<G>(my);
+      const bool owner = head_valid && my == gmin;
+      const uint32_t ostat = group_max<G>(owner ? (uint32_t)(hstat + 1) : 0u);
+      const bool exhausted_any = group_max<G>((!done && !lane_empty && npop >= K) ? 1u : 0u) != 0u;
+      if (!done) {
+        if (exhausted_any) {
+          // some lane must refill its top-K before the group can decide
+        } else if (gmin == kKeyMax) {
+          done = true;          // trapped: every neighbour has been visited
+          win = kKeyMax;
+        } else if (ostat == 2u) {
+          done = true;          // the group's best remaining candidate is new
+          win = gmin;
+        } else if (ostat == 3u) {
+          if (owner) {
+            exclude((head & 0xFFu) / G);
+#pragma unroll
+            for (int i = 0; i + 1 < K; ++i) tk[i] = tk[i + 1];
+            tk[K - 1] = kKeyMax;
+            ++npop;
+            hstat = 0;
+            pstarted = false;
+          }
+        }
+        if (!done && npop >= K && !lane_empty) need_scan = true;
+      }
+      if (__ballot(!done) == 0ull) break;
+    }
+
+    // ---- move -------------------------------------------------------------
+    if (active) {
+      if (win == kKeyMax) {
+        active = false;         // trapped walk stops here
+      } else {
+        const uint32_t jm1 = win & 0xFFu;
+        const int32_t dE = 8 * ((int32_t)(win >> 8) - kBias);
+        CandVec<NW> cv;
+        load_candidate<NW>(desc + jm1 * Gm::DESC, cols, colbase, cv);
+        apply_move_planes<NW>(cv, Pl);
+        // flip sequence positions j and L+1-j (same class) in all arrays
+        const int j = (int)jm1 + 1;
+        const int c = j & 1, nc = c ? n1 : n0, af = c ? 0 : 1;
+        {
+          const int rr = (j - 1) >> 1, rv = nc - 1 - rr;
+          colw[(af * Gm::NWA + (rr >> 5)) * kBlock + tid] ^= 1u << (rr & 31);
+          colw[((af + 2) * Gm::NWA + (rv >> 5)) * kBlock + tid] ^= 1u << (rv & 31);
+        }
+        if (j < D) {
+          const int q = L + 1 - j;
+          const int rr = (q - 1) >> 1, rv = nc - 1 - rr;
+          colw[(af * Gm::NWA + (rr >> 5)) * kBlock + tid] ^= 1u << (rr & 31);
+          colw[((af + 2) * Gm::NWA + (rv >> 5)) * kBlock + tid] ^= 1u << (rv & 31);
+        }
+        const Key3 NP = flip_key(P, jm1);
+        // the lane that probed the winner inserts it at the slot it found
+        const bool owner = hstat == 1 && !lane_empty && npop < K && tk[0] == win;
+        if (owner) store_entry(table + pslot, NP, e32);
+        P = NP;
+        E += dE;
+        if (E < bestE) { bestE = E; bestP = P; }
+        h = mix64(h ^ (((uint64_t)(jm1 + 1u) << 32) | (uint64_t)(uint32_t)E));
+        if (tracing && r == 0) {
+          a.trace_j[walk * a.walk_len + step] = (int16_t)(jm1 + 1u);
+          a.trace_E[walk * a.walk_len + step] = E;
+        }
+        prev_jm1 = jm1;
+        ++steps;
+      }
+    }
+  }
+
+  if (local < a.n_walks && r == 0) {
+    a.best_seq[walk * KW] = bestP.w0;
+    if (KW > 1) a.best_seq[walk * KW + 1] = bestP.w1;
+    if (KW > 2) a.best_seq[walk * KW + 2] = bestP.w2;
+    a.best_E[walk] = bestE;
+    a.steps_done[walk] = steps;
+    if (a.digest) a.digest[walk] = mix64(h ^ (uint64_t)steps);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Energy of full sequences (Eq. 1): one wavefront per sequence, bits in LDS.
+// ---------------------------------------------------------------------------
+constexpr int kEnergyWaves = 4;
+constexpr int kEnergyWords = kEnergyLMax / 32 + 2;
+
+__global__ void __launch_bounds__(64 * kEnergyWaves) energy_kernel(const int8_t *seqs, int32_t L,
+                                                                 int64_t n, int32_t *E_out) {
+  __shared__ uint32_t bits[kEnergyWaves][kEnergyWords];
+  const int wave = (int)threadIdx.x / 64, lane = (int)threadIdx.x % 64;
+  const int nw = (L + 31) / 32;
+  for (int64_t seq = (int64_t)blockIdx.x * kEnergyWaves + wave; seq < n;
+       seq += (int64_t)gridDim.x * kEnergyWaves) {
+    const int8_t *s = seqs + seq * (int64_t)L;
+    for (int base = 0; base < L; base += 64) {
+      const int i = base + lane;
+      const bool neg = i < L && s[i] < 0;
+      const uint64_t bal = __ballot(neg);
+      if (lane == 0) {
+        bits[wave][base / 32] = (uint32_t)bal;
+        if (base / 32 + 1 < kEnergyWords) bits[wave][base / 32 + 1] = (uint32_t)(bal >> 32);
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    int64_t acc = 0;
+    for (int k = 1 + lane; k < L; k += 64) {
+      const int npairs = L - k, q = k >> 5, sh = k & 31;
+      int mism = 0;
+      for (int w = 0; 32 * w < npairs; ++w) {
+        const uint32_t x = bits[wave][w];
+        const uint32_t lo = bits[wave][w + q];
+        const uint32_t hi = (w + q + 1 < kEnergyWords) ? bits[wave][w + q + 1] : 0u;
+        const uint32_t y = funnel(hi, lo, (uint32_t)sh);
+        const int rem = npairs - 32 * w;
+        const uint32_t msk = rem >= 32 ? 0xFFFFFFFFu : ((1u << rem) - 1u);
+        mism += __builtin_popcount((x ^ y) & msk);
+      }
+      const int64_t Ck = (int64_t)npairs - 2 * mism;
+      acc += Ck * Ck;
+    }
+    for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off);
+    if (lane == 0) E_out[seq] = (int32_t)acc;
+    __builtin_amdgcn_wave_barrier();
+  }
+}
+
+__global__ void starts_kernel(int32_t L, int64_t n_walks, uint64_t seed, uint64_t *out) {
+  const int D = (L + 1) / 2, KW = (D + 63) / 64;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < n_walks * KW;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t w = idx / KW;
+    const int t = (int)(idx % KW);
+    uint64_t v = mix64(seed + 0x9E3779B97F4A7C15ull * ((uint64_t)w * (uint64_t)KW + (uint64_t)t + 1u));
+    const int bits = D - 64 * t;
+    if (bits < 64) v &= ((1ull << bits) - 1ull);
+    out[idx] = v;
+  }
+}
+
+__global__ void clear_kernel(uint4 *p, uint64_t n16) {
+  const uint4 z = {0u, 0u, 0u, 0u};
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16;
+       i += (uint64_t)gridDim.x * blockDim.x)
+    p[i] = z;
+}
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+hipError_t launch_energy(const int8_t *seqs, int32_t L, int64_t n, int32_t *E_out,
+                         hipStream_t stream) {
+  if (n == 0) return hipSuccess;
+  int64_t blocks = (n + kEnergyWaves - 1) / kEnergyWaves;
+  if (blocks > 65535) blocks = 65535;
+  hipLaunchKernelGGL(energy_kernel, dim3((unsigned)blocks), dim3(64 * kEnergyWaves), 0, stream,
+                     seqs, L, n, E_out);
+  return hipGetLastError();
+}
+
+hipError_t launch_starts(int32_t L, int64_t n_walks, uint64_t seed, uint64_t *out,
+                         hipStream_t stream) {
+  if (n_walks == 0) return hipSuccess;
+  const int KW = key_words_for(L);
+  int64_t blocks = (n_walks * KW + 255) / 256;
+  if (blocks > 65535) blocks = 65535;
+  hipLaunchKernelGGL(starts_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, L, n_walks, seed, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_clear(uint8_t *p, uint64_t bytes, hipStream_t stream) {
+  if (bytes == 0) return hipSuccess;
+  const uint64_t n16 = bytes / 16;
+  uint64_t blocks = (n16 + 255) / 256;
+  if (blocks > 1u << 20) blocks = 1u << 20;
+  hipLaunchKernelGGL(clear_kernel, dim3((unsigned)blocks), dim3(256), 0, stream,
+                     reinterpret_cast<uint4 *>(p), n16);
+  return hipGetLastError();
+}
+
+template <int NW>
+static size_t lds_for() { return Geom<NW>::lds_bytes(); }
+
+size_t walk_lds_bytes(int32_t L) {
+  switch (lag_words_for(L)) {
+    case 1: return lds_for<1>();
+    case 2: return lds_for<2>();
+    case 3: return lds_for<3>();
+    case 4: return lds_for<4>();
+    case 5: return lds_for<5>();
+    case 6: return lds_for<6>();
+    default: return 0;
+  }
+}
+
+template <int NW, int G>
+static hipError_t launch_nw_g(const WalkLaunch &w, hipStream_t stream) {
+  constexpr int K = (G == 1) ? 4 : 2;
+  const size_t lds = Geom<NW>::lds_bytes();
+  auto kern = walk_kernel<NW, G, K>;
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  const int64_t per_block = kBlock / G;
+  const int64_t blocks = (w.n_walks + per_block - 1) / per_block;
+  if (blocks == 0) return hipSuccess;
+  hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(kBlock), lds, stream, w);
+  return hipGetLastError();
+}
+
+template <int NW>
+static hipError_t launch_nw(const WalkLaunch &w, hipStream_t stream) {
+  switch (w.lanes_per_walk) {
+    case 1: return launch_nw_g<NW, 1>(w, stream);
+    case 2: return launch_nw_g<NW, 2>(w, stream);
+    case 4: return launch_nw_g<NW, 4>(w, stream);
+    case 8: return launch_nw_g<NW, 8>(w, stream);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_walks(const WalkLaunch &w, hipStream_t stream) {
+  switch (lag_words_for(w.L)) {
+    case 1: return launch_nw<1>(w, stream);
+    case 2: return launch_nw<2>(w, stream);
+    case 3: return launch_nw<3>(w, stream);
+    case 4: return launch_nw<4>(w, stream);
+    case 5: return launch_nw<5>(w, stream);
+    case 6: return launch_nw<6>(w, stream);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace lsaw

@@ -1,0 +1,226 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Integer work, so the bar is bit-exact: traces (j, E per move), best energy,
+best sequence, steps done and the per-walk digest.  Inputs are seeded
+(labs_inputs) or drawn by each side's own SplitMix64 from the same seed.
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+import labs_inputs as I
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(autouse=True)
+def _announce(request):
+    print(f"\n[case] {request.node.name}", flush=True)
+    yield
+
+
+def _labs():
+    from paper_2210_15962_amd import labs
+    return labs
+
+
+def _u64(t):
+    return t.cpu().numpy().view(np.uint64)
+
+
+def run_gpu(L, keys, walk_len, n_trace=0, plan=None, workspace=None):
+    labs = _labs()
+    n = keys.shape[0]
+    st = torch.from_numpy(I.as_int64_keys(keys)).cuda()
+    res = labs.walks(L, n, walk_len, starts_t=st, n_trace=n_trace, plan=plan, workspace=workspace)
+    torch.cuda.synchronize()
+    return res
+
+
+_ORACLE_CACHE = {}
+
+
+def oracle_walks(L, keys, walk_len):
+    k = (L, walk_len, keys.tobytes())
+    if k not in _ORACLE_CACHE:
+        _ORACLE_CACHE[k] = O.walks(L, keys, walk_len)
+    return _ORACLE_CACHE[k]
+
+
+def oracle_walk(L, key, walk_len):
+    k = ("one", L, walk_len, key.tobytes())
+    if k not in _ORACLE_CACHE:
+        _ORACLE_CACHE[k] = O.walk(L, key, walk_len)
+    return _ORACLE_CACHE[k]
+
+
+def assert_matches_oracle(L, keys, walk_len, res, traced=()):
+    ref = oracle_walks(L, keys, walk_len)
+    np.testing.assert_array_equal(res["best_E"].cpu().numpy(), ref["best_E"])
+    np.testing.assert_array_equal(res["steps_done"].cpu().numpy(), ref["steps_done"])
+    np.testing.assert_array_equal(_u64(res["best_seq"]), ref["best_seq"])
+    np.testing.assert_array_equal(_u64(res["digest"]), ref["digest"])
+    for i in traced:
+        r = oracle_walk(L, keys[i], walk_len)
+        tj = res["trace_j"][i].cpu().numpy()[: r.steps]
+        tE = res["trace_E"][i].cpu().numpy()[: r.steps]
+        np.testing.assert_array_equal(tj, r.trace_j)
+        np.testing.assert_array_equal(tE, r.trace_E)
+
+
+# ------------------------------------------------------------------ energy
+@pytest.mark.parametrize("L", [1, 2, 3, 13, 31, 32, 33, 63, 64, 65, 127, 151, 255, 301, 512, 1024])
+def test_energy_random_sequences(L):
+    labs = _labs()
+    seqs = I.random_pm1(97, L, seed=L)
+    E = labs.energy(torch.from_numpy(seqs).cuda()).cpu().numpy()
+    assert [int(e) for e in E] == [O.energy(s) for s in seqs]
+
+
+def test_energy_table1_and_constant_sequences():
+    labs = _labs()
+    rows = []
+    import os
+    with open(os.path.join(os.path.dirname(__file__), "golden", "table1_new_best_sequences.txt")) as f:
+        for line in f:
+            if line.startswith("#") or not line.strip():
+                continue
+            L, E, F, code = line.split()
+            rows.append((int(L), int(E), code))
+    for L, E, code in rows:
+        s = O.expand_skew(O.decode_table_hex(code, L), L)
+        got = labs.energy(torch.from_numpy(s[None, :]).cuda()).item()
+        assert got == E
+    ones = torch.ones((3, 1024), dtype=torch.int8).cuda()
+    assert labs.energy(ones).cpu().tolist() == [1023 * 1024 * 2047 // 6] * 3
+    assert labs.energy(torch.empty((0, 5), dtype=torch.int8).cuda()).numel() == 0
+
+
+# ------------------------------------------------------------------ starts
+@pytest.mark.parametrize("L", [3, 27, 101, 127, 129, 151, 255, 301, 383])
+def test_seeded_starts_match_oracle(L):
+    labs = _labs()
+    for seed in [0, 1, 2 ** 63 + 5]:
+        got = _u64(labs.starts(L, 300, seed))
+        np.testing.assert_array_equal(got, O.starts(L, 300, seed))
+
+
+# ------------------------------------------------------------------ walks
+def test_config1_all_walks_bit_exact():
+    """L=27, 64 walks from seed 0, 4096 moves: every trace, best and digest."""
+    labs = _labs()
+    L, n, steps = 27, 64, 4096
+    res = labs.walks(L, n, steps, seed=0, n_trace=n)
+    torch.cuda.synchronize()
+    keys = O.starts(L, n, 0)
+    assert_matches_oracle(L, keys, steps, res, traced=range(n))
+    mn, cnt, first, total = O.bruteforce(L)
+    assert res["best_E"].min().item() == mn
+
+
+@pytest.mark.parametrize("G", [1, 2, 4, 8])
+@pytest.mark.parametrize("L,steps,n", [
+    (3, 20, 9), (5, 20, 9), (7, 100, 16), (9, 300, 16), (11, 200, 16), (21, 300, 24),
+    (33, 300, 12), (63, 200, 12), (65, 200, 12),            # one lag word
+    (67, 200, 10), (99, 200, 8), (127, 150, 8), (129, 150, 8),  # two lag words
+    (131, 120, 6), (151, 120, 6), (193, 100, 5),          # three
+    (195, 80, 4), (253, 60, 4), (255, 60, 4), (257, 60, 4),  # four (32-byte entries from 255)
+    (259, 40, 3), (301, 40, 3), (321, 40, 3),             # five
+    (323, 30, 3), (383, 30, 3),                           # six
+])
+def test_walks_match_oracle_across_lengths(L, steps, n, G):
+    labs = _labs()
+    keys = I.random_start_keys(L, n, seed=1000 + L)
+    res = run_gpu(L, keys, steps, n_trace=n, plan=labs.make_plan(lanes_per_walk=G))
+    assert_matches_oracle(L, keys, steps, res, traced=range(min(n, 3)))
+
+
+@pytest.mark.parametrize("G", [1, 2, 4, 8])
+def test_trapped_walks_stop_like_the_oracle(G):
+    labs = _labs()
+    for L in (3, 5, 7):
+        keys = I.random_start_keys(L, 32, seed=L)
+        res = run_gpu(L, keys, 100, n_trace=32, plan=labs.make_plan(lanes_per_walk=G))
+        assert (res["steps_done"].cpu().numpy() < 2 ** ((L + 1) // 2)).all()
+        assert_matches_oracle(L, keys, 100, res, traced=range(32))
+
+
+def test_hand_derived_walk_L5():
+    res = run_gpu(5, O.pack([1, 1, 1])[None, :], 50, n_trace=1)
+    assert res["steps_done"].item() == 6
+    assert res["trace_j"][0, :6].cpu().tolist() == [2, 1, 3, 2, 1, 2]
+    assert res["trace_E"][0, :6].cpu().tolist() == [2, 10, 2, 2, 10, 10]
+
+
+def test_walk_len_zero_returns_starts():
+    L = 151
+    keys = I.random_start_keys(L, 50, seed=4)
+    res = run_gpu(L, keys, 0)
+    np.testing.assert_array_equal(_u64(res["best_seq"]), keys)
+    assert res["best_E"].cpu().tolist() == [O.energy_packed(k, L) for k in keys]
+    assert res["steps_done"].cpu().tolist() == [0] * 50
+    assert _u64(res["digest"]).tolist() == [0] * 50
+
+
+def test_results_independent_of_plan_and_chunking():
+    """Lanes per walk, table load factor and workspace chunking change speed only."""
+    labs = _labs()
+    L, n, steps = 101, 300, 1500
+    keys = I.random_start_keys(L, n, seed=77)
+    ref = None
+    for G in (1, 2, 4, 8):
+        for lf in (0.25, 0.5, 0.8):
+            plan = labs.make_plan(lanes_per_walk=G, load_factor=lf)
+            res = run_gpu(L, keys, steps, plan=plan)
+            got = (_u64(res["digest"]), res["best_E"].cpu().numpy(), _u64(res["best_seq"]))
+            if ref is None:
+                ref = got
+            else:
+                for a, b in zip(got, ref):
+                    np.testing.assert_array_equal(a, b)
+    # a workspace for 37 walks forces 9 consecutive chunks
+    plan = labs.make_plan(lanes_per_walk=2)
+    ws = labs.alloc_workspace(37 * labs.min_workspace_bytes(L, steps, plan))
+    res = run_gpu(L, keys, steps, plan=plan, workspace=ws)
+    np.testing.assert_array_equal(_u64(res["digest"]), ref[0])
+    # and the oracle agrees on a sample
+    idx = I.sample_indices(n, 4, 4, seed=1)
+    r = O.walks(L, keys[idx], steps)
+    np.testing.assert_array_equal(ref[0][idx], r["digest"])
+
+
+def test_seeded_walks_equal_explicit_starts():
+    labs = _labs()
+    L, n, steps = 61, 200, 800
+    a = labs.walks(L, n, steps, seed=12345)
+    keys = O.starts(L, n, 12345)
+    b = run_gpu(L, keys, steps)
+    np.testing.assert_array_equal(_u64(a["digest"]), _u64(b["digest"]))
+    np.testing.assert_array_equal(a["best_E"].cpu().numpy(), b["best_E"].cpu().numpy())
+
+
+def test_repeated_runs_identical():
+    labs = _labs()
+    L, n, steps = 151, 512, 600
+    keys = I.random_start_keys(L, n, seed=8)
+    d = [_u64(run_gpu(L, keys, steps)["digest"]) for _ in range(3)]
+    np.testing.assert_array_equal(d[0], d[1])
+    np.testing.assert_array_equal(d[0], d[2])
+
+
+def test_best_sequence_energy_recomputed():
+    """E(best_seq) by the energy kernel and by the oracle equals best_E."""
+    labs = _labs()
+    L, n, steps = 101, 1024, 3000
+    keys = I.random_start_keys(L, n, seed=21)
+    res = run_gpu(L, keys, steps)
+    best = _u64(res["best_seq"])
+    x = labs.unpack_skew(best, L)
+    s = labs.expand_skew(x, L)
+    E = labs.energy(torch.from_numpy(s).cuda()).cpu().numpy()
+    np.testing.assert_array_equal(E, res["best_E"].cpu().numpy())
+    for i in range(0, n, 97):
+        assert O.energy_packed(best[i], L) == int(E[i])
+    m = (L - 1) // 2
+    assert ((E - m) % 8 == 0).all() and (E >= m).all()
