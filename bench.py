@@ -1,0 +1,198 @@
+"""Benchmark of the skew-symmetric LABS walk engine on one MI355X.
+
+A step is one pass of the whole hot path over one batch of synthetic input:
+labs_walks over the headline workload (L = 151, 65,536 walks of 131,072 moves
+from seeded uniform starts).  Prints one JSON line with walk steps/s (Sum of
+steps_done over the timed steps / time), neighbour evaluations/s, the INT32
+VALU roofline of the walk kernel and the CPU oracle baseline.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# Headline workload: walks at L = 151.  At load factor 0.67 the 65,536 visited
+# tables (131,073 keys each, 16-byte entries) take 191 GiB, so every walk stays
+# resident in one launch.
+WORKLOAD = dict(L=151, n_walks=65536, walk_len=131072)
+
+# MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz, one 32-bit lane-op per cycle.
+INT32_VALU_PEAK = 256 * 4 * 16 * 2.4e9
+
+
+def lag_words(L: int) -> int:
+    return ((L - 1) // 2 + 31) // 32
+
+
+def planes_of(nw: int, w: int) -> int:
+    lmax = min(64 * nw + 1, 383)
+    mx = (lmax - 64 * w - 1) // 2
+    b = 0
+    while (1 << b) < mx:
+        b += 1
+    return 1 + b
+
+
+def ops_per_candidate(L: int) -> int:
+    """Algorithmic 32-bit lane-ops of one neighbour evaluation in the
+    bit-sliced form: one 3-input bitwise op and one popcount per plane word,
+    forward (NW words), backward (ceil(NW/2) words) and the u^2 term."""
+    nw = lag_words(L)
+    nwb = (nw + 1) // 2
+    pw = sum(planes_of(nw, w) for w in range(nw)) + sum(planes_of(nw, w) for w in range(nwb)) + nwb
+    return 2 * pw
+
+
+def kernel_source_tag() -> str:
+    import hashlib
+    src = os.path.join(ROOT, "paper_2210_15962_amd", "csrc", "labs_kernels.hip")
+    with open(src, "rb") as f:
+        return hashlib.sha1(f.read()).hexdigest()[:12]
+
+
+def load_counter_traffic(kernel_tag: str):
+    """HBM bytes per launch measured by rocprofv3 --pmc, if recorded for this
+    kernel build (profiles/<name>.json written from the counter runs)."""
+    path = os.path.join(ROOT, "profiles", "walk_kernel_L151_traffic.json")
+    try:
+        with open(path) as f:
+            d = json.load(f)
+        if d.get("kernel_tag") == kernel_tag:
+            return d.get("bytes_per_launch")
+    except (OSError, ValueError):
+        pass
+    return None
+
+
+def cpu_baseline(L: int, seconds_target: float = 15.0):
+    """The CPU oracle (untuned) on a bounded sample of the same workload."""
+    import numpy as np
+    from oracle import oracle as O
+    cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    cores = max(1, min(cores, 64))
+    # calibrate: one walk of 256 moves on one core
+    st = O.starts(L, cores, seed=0)
+    t0 = time.time()
+    O.walk(L, st[0], 256, trace=False)
+    per_step = (time.time() - t0) / 256
+    steps = int(max(256, min(131072, seconds_target / max(per_step, 1e-9))))
+    t0 = time.time()
+    res = O.walks(L, st, steps, n_threads=cores)
+    dt = time.time() - t0
+    total = int(res["steps_done"].sum())
+    return {"value": total / dt, "unit": "walk steps/s", "cores": cores, "kind": "oracle",
+            "sample": f"{cores} walks x {steps} moves at L={L} (seed 0 starts), "
+                      f"one walk per host thread, {dt:.1f} s wall"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--lanes", type=int, default=4, help="lanes per walk")
+    ap.add_argument("--concurrent", type=int, default=65536, help="walks resident at once")
+    ap.add_argument("--load-factor", type=float, default=0.67)
+    ap.add_argument("--walk-len", type=int, default=WORKLOAD["walk_len"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibration-copy-mib", type=int, default=0,
+                    help="run one plain device copy of this size first (counter calibration)")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
+              "(walks are independent: N GPUs would each run their own batch).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2210_15962_amd import labs
+
+    L, n = WORKLOAD["L"], WORKLOAD["n_walks"]
+    walk_len = args.walk_len
+    D = (L + 1) // 2
+    plan = labs.make_plan(lanes_per_walk=args.lanes, load_factor=args.load_factor,
+                          max_concurrent=args.concurrent)
+    conc = min(n, args.concurrent)
+    launches = (n + conc - 1) // conc
+    ws = labs.alloc_workspace(labs.workspace_bytes(L, n, walk_len, plan))
+    stream = torch.cuda.current_stream()
+    if args.calibration_copy_mib:
+        nb = args.calibration_copy_mib << 20
+        src_t = torch.ones(nb, dtype=torch.uint8, device="cuda")
+        dst_t = torch.empty_like(src_t)
+        dst_t.copy_(src_t)
+        torch.cuda.synchronize()
+        del src_t, dst_t
+
+    def one_step(seed):
+        return labs.walks(L, n, walk_len, seed=seed, plan=plan, workspace=ws)
+
+    for w in range(args.warmup):
+        one_step(1000 + w)
+    torch.cuda.synchronize()
+
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    total_steps = 0
+    kernel_ms = 0.0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    results = []
+    for s in range(args.steps):
+        ev0.record(stream)
+        res = one_step(s)
+        ev1.record(stream)
+        results.append(res["steps_done"])
+        ev1.synchronize()
+        kernel_ms += ev0.elapsed_time(ev1)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    total_steps = int(sum(int(r.sum().item()) for r in results))
+
+    steps_per_s = total_steps / wall
+    avg_launch_s = kernel_ms / 1e3 / (args.steps * launches)
+    alg_ops_per_launch = (total_steps / (args.steps * launches)) * D * ops_per_candidate(L)
+    achieved = alg_ops_per_launch / avg_launch_s
+    tag = f"walk_kernel<NW={lag_words(L)},G={args.lanes}>@{kernel_source_tag()}"
+    traffic = load_counter_traffic(tag)
+
+    out = {
+        "metric": "walk steps/s & neighbour evals/s at L=151 (% INT32 peak); served p50/p99 latency",
+        "value": steps_per_s,
+        "unit": "walk steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": f"skew-symmetric LABS self-avoiding walks, L={L}, {n} walks x "
+                               f"{walk_len} moves, seeded uniform starts",
+                   "L": L, "n_walks": n, "walk_len": walk_len, "lanes_per_walk": args.lanes,
+                   "walks_resident": conc, "launches_per_step": launches,
+                   "load_factor": args.load_factor},
+        "neighbour_evals_per_s": steps_per_s * D,
+        "paper_evals_per_s": steps_per_s * (D - 1),
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": INT32_VALU_PEAK / 1e12,
+                     "unit": "TOP/s", "frac": achieved / INT32_VALU_PEAK, "traffic": traffic,
+                     "kernel": tag, "avg_launch_ms": avg_launch_s * 1e3,
+                     "alg_ops_per_launch": alg_ops_per_launch,
+                     "ops_per_neighbour_eval": ops_per_candidate(L)},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(L)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

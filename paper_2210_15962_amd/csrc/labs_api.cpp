@@ -224,9 +224,7 @@ int32_t labs_walks(const uint64_t *starts, int32_t L, int64_t n_walks, int64_t w
     w.table_bytes = p.table_bytes;
     w.n_buckets = p.n_buckets;
     w.lanes_per_walk = G;
-    hipError_t e = lsaw::launch_clear(w.tables, (uint64_t)cnt * p.table_bytes, st);
-    if (e != hipSuccess) return fail(LABS_EDEVICE, "clear launch: %s", hipGetErrorString(e));
-    e = lsaw::launch_walks(w, st);
+    hipError_t e = lsaw::launch_walks(w, st);
     if (e != hipSuccess) return fail(LABS_EDEVICE, "walk launch: %s", hipGetErrorString(e));
   }
   return ok();

@@ -43,7 +43,6 @@ hipError_t launch_energy(const int8_t *seqs, int32_t L, int64_t n, int32_t *E_ou
                          hipStream_t stream);
 hipError_t launch_starts(int32_t L, int64_t n_walks, uint64_t seed, uint64_t *out,
                          hipStream_t stream);
-hipError_t launch_clear(uint8_t *p, uint64_t bytes, hipStream_t stream);
 hipError_t launch_walks(const WalkLaunch &w, hipStream_t stream);
 // Dynamic LDS bytes the walk kernel needs for length L (0 if unsupported).
 size_t walk_lds_bytes(int32_t L);

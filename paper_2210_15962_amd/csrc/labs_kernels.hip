@@ -399,6 +399,16 @@ __global__ void __launch_bounds__(kBlock) walk_kernel(const WalkLaunch a) {
   const int L = a.L, D = (L + 1) / 2, m = (L - 1) / 2;
   const int KW = (D + 63) / 64;
   build_descriptors<NW>(desc, L);
+  {
+    // Clear the visited tables of this block's walks (contiguous, coalesced).
+    const int64_t first = (int64_t)blockIdx.x * (kBlock / G);
+    const int64_t nwb = min((int64_t)(kBlock / G), a.n_walks - first);
+    uint4 *p = reinterpret_cast<uint4 *>(a.tables + (uint64_t)first * a.table_bytes);
+    const uint64_t n16 = (uint64_t)nwb * (a.table_bytes / 16u);
+    const uint4 z = {0u, 0u, 0u, 0u};
+#pragma unroll 4
+    for (uint64_t i = threadIdx.x; i < n16; i += kBlock) p[i] = z;
+  }
   __syncthreads();
 
   const int tid = (int)threadIdx.x;
@@ -716,13 +726,6 @@ __global__ void starts_kernel(int32_t L, int64_t n_walks, uint64_t seed, uint64_
   }
 }
 
-__global__ void clear_kernel(uint4 *p, uint64_t n16) {
-  const uint4 z = {0u, 0u, 0u, 0u};
-  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16;
-       i += (uint64_t)gridDim.x * blockDim.x)
-    p[i] = z;
-}
-
 // ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
@@ -743,16 +746,6 @@ hipError_t launch_starts(int32_t L, int64_t n_walks, uint64_t seed, uint64_t *ou
   int64_t blocks = (n_walks * KW + 255) / 256;
   if (blocks > 65535) blocks = 65535;
   hipLaunchKernelGGL(starts_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, L, n_walks, seed, out);
-  return hipGetLastError();
-}
-
-hipError_t launch_clear(uint8_t *p, uint64_t bytes, hipStream_t stream) {
-  if (bytes == 0) return hipSuccess;
-  const uint64_t n16 = bytes / 16;
-  uint64_t blocks = (n16 + 255) / 256;
-  if (blocks > 1u << 20) blocks = 1u << 20;
-  hipLaunchKernelGGL(clear_kernel, dim3((unsigned)blocks), dim3(256), 0, stream,
-                     reinterpret_cast<uint4 *>(p), n16);
   return hipGetLastError();
 }
 
