@@ -1,0 +1,104 @@
+"""Parity at the full workload sizes, in the launch configuration bench.py times.
+
+The oracle recomputes every neighbour energy (O(D L^2) per move), so it checks
+sampled walks: whole walks at L = 101 (65,536 moves) and trace prefixes at
+L = 151 (a walk's first t moves do not depend on its length).  Properties that
+hold at any size are checked on every walk: E(best_seq) recomputed by the
+energy kernel equals best_E, best_E = m (mod 8), best_E >= m, and digests do
+not depend on the launch plan.
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+import labs_inputs as I
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(autouse=True)
+def _announce(request):
+    print(f"\n[case] {request.node.name}", flush=True)
+    yield
+    torch.cuda.empty_cache()
+
+
+def _labs():
+    from paper_2210_15962_amd import labs
+    return labs
+
+
+def _u64(t):
+    return t.cpu().numpy().view(np.uint64)
+
+
+def check_best_energies(L, res):
+    labs = _labs()
+    best = _u64(res["best_seq"])
+    E_best = res["best_E"].cpu().numpy()
+    s = labs.expand_skew(labs.unpack_skew(best, L), L)
+    E = np.concatenate([labs.energy(torch.from_numpy(s[i:i + 16384]).cuda()).cpu().numpy()
+                        for i in range(0, len(s), 16384)])
+    np.testing.assert_array_equal(E, E_best)
+    m = (L - 1) // 2
+    assert ((E_best - m) % 8 == 0).all() and (E_best >= m).all()
+    return best, E_best
+
+
+def test_config2_L101_16384_walks_65536_moves():
+    labs = _labs()
+    L, n, steps = 101, 16384, 65536
+    res = labs.walks(L, n, steps, seed=0, n_trace=2)
+    torch.cuda.synchronize()
+    best, E_best = check_best_energies(L, res)
+    keys = O.starts(L, n, 0)
+    idx = I.sample_indices(n, 8, 8, seed=2)
+    ref = O.walks(L, keys[idx], steps)
+    np.testing.assert_array_equal(E_best[idx], ref["best_E"])
+    np.testing.assert_array_equal(best[idx], ref["best_seq"])
+    np.testing.assert_array_equal(res["steps_done"].cpu().numpy()[idx], ref["steps_done"])
+    np.testing.assert_array_equal(_u64(res["digest"])[idx], ref["digest"])
+    for i in range(2):
+        r = O.walk(L, keys[i], steps)
+        np.testing.assert_array_equal(res["trace_j"][i].cpu().numpy()[: r.steps], r.trace_j)
+        np.testing.assert_array_equal(res["trace_E"][i].cpu().numpy()[: r.steps], r.trace_E)
+    # another plan (1 lane per walk, 4 chunks) gives the same digests
+    plan = labs.make_plan(lanes_per_walk=1, load_factor=0.4, max_concurrent=4096)
+    res2 = labs.walks(L, n, steps, seed=0, plan=plan)
+    np.testing.assert_array_equal(_u64(res2["digest"]), _u64(res["digest"]))
+
+
+def test_config3_L151_65536_walks_131072_moves_bench_plan():
+    labs = _labs()
+    L, n, steps = 151, 65536, 131072
+    plan = labs.make_plan(lanes_per_walk=4, load_factor=0.67, max_concurrent=65536)
+    ws = labs.alloc_workspace(labs.workspace_bytes(L, n, steps, plan))
+    res = labs.walks(L, n, steps, seed=0, plan=plan, workspace=ws, n_trace=4)
+    torch.cuda.synchronize()
+    del ws
+    torch.cuda.empty_cache()
+    check_best_energies(L, res)
+    sd = res["steps_done"].cpu().numpy()
+    assert (sd <= steps).all()
+    keys = O.starts(L, n, 0)
+    # trace prefixes of the traced walks
+    prefix = 6000
+    for i in range(4):
+        r = O.walk(L, keys[i], prefix)
+        np.testing.assert_array_equal(res["trace_j"][i].cpu().numpy()[: r.steps], r.trace_j)
+        np.testing.assert_array_equal(res["trace_E"][i].cpu().numpy()[: r.steps], r.trace_E)
+    # the first walks again under a different plan: identical digests and bests
+    sub = 2048
+    plan2 = labs.make_plan(lanes_per_walk=8, load_factor=0.5)
+    res2 = labs.walks(L, sub, steps, seed=0, plan=plan2)
+    np.testing.assert_array_equal(_u64(res2["digest"]), _u64(res["digest"])[:sub])
+    np.testing.assert_array_equal(res2["best_E"].cpu().numpy(), res["best_E"].cpu().numpy()[:sub])
+    # sampled walks, prefix-length runs, against the oracle (a prefix run of the
+    # GPU path with explicit starts equals the oracle's prefix run)
+    idx = I.sample_indices(n, 4, 4, seed=3)
+    st = torch.from_numpy(I.as_int64_keys(keys[idx])).cuda()
+    short = labs.walks(L, len(idx), prefix, starts_t=st, plan=plan)
+    ref = O.walks(L, keys[idx], prefix)
+    np.testing.assert_array_equal(short["best_E"].cpu().numpy(), ref["best_E"])
+    np.testing.assert_array_equal(_u64(short["digest"]), ref["digest"])
