@@ -93,6 +93,60 @@ def cpu_baseline(L: int, seconds_target: float = 15.0):
                       f"one walk per host thread, {dt:.1f} s wall"}
 
 
+def serve_workload(n_req: int, rate: float, seed: int = 0):
+    """Served stream: Poisson arrivals, L uniform odd in [121, 301], 4096 walks
+    x 65,536 moves per request from seeded starts."""
+    import labs_inputs as I
+    Ls = I.odd_lengths(n_req, 121, 301, seed=seed)
+    t = I.poisson_arrivals(rate, n_req, seed=seed + 1)
+    return [dict(L=int(L), n_walks=4096, walk_len=65536, seed=10_000 + i, t_arrive=float(t[i]))
+            for i, L in enumerate(Ls)]
+
+
+def run_serving(n_req: int, rate: float, load_factor: float, chunk: int, pool_frac: float = 0.85):
+    """Serve the stream through labs_serve_* and run the same requests as one
+    plain mixed-L batch; returns latency percentiles and both throughputs."""
+    import numpy as np
+    import torch
+    from paper_2210_15962_amd import labs
+    reqs = serve_workload(n_req, rate)
+    free, _ = torch.cuda.mem_get_info()
+    pool = int(free * pool_frac)
+    with labs.Server(pool_bytes=pool, load_factor=load_factor, chunk_steps=chunk) as srv:
+        ids = []
+        t0 = time.perf_counter()
+        for q in reqs:
+            dt = q["t_arrive"] - (time.perf_counter() - t0)
+            if dt > 0:
+                time.sleep(dt)
+            ids.append(srv.submit(q["L"], q["n_walks"], q["walk_len"], q["seed"]))
+        res = [srv.wait(i) for i in ids]
+        st = srv.stats()
+    lat = np.array([(r["t_done_ns"] - r["t_submit_ns"]) / 1e6 for r in res])
+    steps = sum(r["total_steps"] for r in res)
+    span = (max(r["t_done_ns"] for r in res) - min(r["t_submit_ns"] for r in res)) / 1e9
+    served = steps / span
+    torch.cuda.empty_cache()
+    # the same requests as one plain batch (one persistent launch)
+    specs = [dict(L=q["L"], n_walks=q["n_walks"], walk_len=q["walk_len"], seed=q["seed"],
+                  load_factor=load_factor) for q in reqs]
+    torch.cuda.synchronize()
+    tb = time.perf_counter()
+    out = labs.walks_batch(specs)
+    torch.cuda.synchronize()
+    tb = time.perf_counter() - tb
+    bsteps = int(sum(int(o["steps_done"].sum().item()) for o in out))
+    del out
+    torch.cuda.empty_cache()
+    return {"rate_req_per_s": rate, "requests": n_req, "walks_per_request": 4096,
+            "moves_per_walk": 65536, "L_range": [121, 301], "chunk_steps": chunk,
+            "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+            "served_steps_per_s": served, "served_busy_steps_per_s": steps / (st["busy_ns"] / 1e9),
+            "batch_steps_per_s": bsteps / tb, "served_over_batch": served / (bsteps / tb),
+            "launches": st["launches"], "pool_gib": st["pool_bytes"] / 2**30,
+            "pool_peak_gib": st["pool_peak"] / 2**30, "identical_steps": steps == bsteps}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -105,6 +159,12 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibration-copy-mib", type=int, default=0,
                     help="run one plain device copy of this size first (counter calibration)")
+    ap.add_argument("--serve-requests", type=int, default=24)
+    ap.add_argument("--serve-rate", type=float, default=10.0)
+    ap.add_argument("--serve-chunk", type=int, default=8192)
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-sweep", type=str, default="",
+                    help="comma-separated arrival rates: serve only, one JSON line per rate")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -114,6 +174,12 @@ def main():
 
     import torch
     from paper_2210_15962_amd import labs
+
+    if args.serve_sweep:
+        for rate in [float(x) for x in args.serve_sweep.split(",")]:
+            print(json.dumps(run_serving(args.serve_requests, rate, args.load_factor, args.serve_chunk)),
+                  flush=True)
+        return
 
     L, n = WORKLOAD["L"], WORKLOAD["n_walks"]
     walk_len = args.walk_len
@@ -189,6 +255,11 @@ def main():
                      "alg_ops_per_launch": alg_ops_per_launch,
                      "ops_per_neighbour_eval": ops_per_candidate(L)},
     }
+    del ws
+    torch.cuda.empty_cache()
+    if not args.no_serve:
+        out["serving"] = run_serving(args.serve_requests, args.serve_rate, args.load_factor,
+                                     args.serve_chunk)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(L)
     print(json.dumps(out), flush=True)

@@ -54,11 +54,11 @@ int32_t labs_key_words(int32_t L);
 /*
  * labs_energy -- Eq. 1: E(S) = sum_{k=1}^{L-1} C_k^2 with
  * C_k = sum_{i=1}^{L-k} s_i s_{i+k}, for n full sequences of any length
- * 1 <= L <= 8192 (skew-symmetric or not).
+ * 1 <= L <= 1024 (skew-symmetric or not; every such E fits int32).
  *   seqs  device int8 [n][L], each element +1 or -1 (other values give an
  *         unspecified result; the Python binding validates them).
  *   E_out device int32 [n].
- * Errors: LABS_EINVAL if L < 1, L > 8192, n < 0 or a pointer is NULL while
+ * Errors: LABS_EINVAL if L < 1, L > 1024, n < 0 or a pointer is NULL while
  * n > 0.
  */
 int32_t labs_energy(const int8_t *seqs, int32_t L, int64_t n, int32_t *E_out,
@@ -147,6 +147,145 @@ int32_t labs_walks(const uint64_t *starts, int32_t L, int64_t n_walks,
                    int64_t walk_len, uint64_t seed, const labs_walk_out *out,
                    void *workspace, uint64_t ws_bytes, const labs_plan *plan,
                    void *stream);
+
+
+/*
+ * Mixed-length batches (several instances of different L in one launch).
+ * An instance is one labs_walks job; all instances of a batch run in a
+ * single persistent launch that drains a device work queue of
+ * (instance, block of walks) items.  Results are identical to running each
+ * instance alone with labs_walks.
+ *   lanes_per_walk : 0 = tuned table (labs_tune_set / labs_autotune) or the
+ *                    built-in default, else 2, 4 or 8.
+ *   load_factor    : 0 = tuned table or 0.5, else in (0, 0.9].
+ *   starts         : device [n_walks][W] or NULL (seeded from `seed`).
+ *   out            : per-instance outputs as for labs_walks (device pointers).
+ */
+typedef struct labs_instance {
+  int32_t L;
+  int32_t lanes_per_walk;
+  int64_t n_walks;
+  int64_t walk_len;
+  uint64_t seed;
+  const uint64_t *starts;
+  double load_factor;
+  labs_walk_out out;
+} labs_instance;
+
+/*
+ * labs_batch_workspace_bytes -- workspace for labs_walks_batch /
+ * labs_batch_graph_create: queue control, the work-item list and one visited-
+ * table arena per resident workgroup of the current device (queries the
+ * device; LABS_EDEVICE without one).  Smaller workspaces run with fewer
+ * resident workgroups.
+ */
+int32_t labs_batch_workspace_bytes(const labs_instance *inst, int32_t n_inst, uint64_t *bytes);
+
+/*
+ * labs_walks_batch -- run every instance (host array inst[0..n_inst-1]) in one
+ * persistent launch on `stream`.  The work-item list is uploaded into the
+ * workspace with an asynchronous copy from host memory.  Errors: LABS_EINVAL
+ * (any invalid instance, workspace below one arena), LABS_EDEVICE.
+ */
+int32_t labs_walks_batch(const labs_instance *inst, int32_t n_inst, void *workspace,
+                         uint64_t ws_bytes, void *stream);
+
+/*
+ * hipGraph form of labs_walks_batch: create uploads the work items once and
+ * captures the queue reset and the persistent launch into an executable
+ * graph; launch replays it on `stream` (each replay recomputes the same
+ * results into the same output buffers); destroy releases the graph.
+ */
+typedef struct labs_batch_graph labs_batch_graph;
+int32_t labs_batch_graph_create(const labs_instance *inst, int32_t n_inst, void *workspace,
+                                uint64_t ws_bytes, labs_batch_graph **graph);
+int32_t labs_batch_graph_launch(labs_batch_graph *graph, void *stream);
+int32_t labs_batch_graph_destroy(labs_batch_graph *graph);
+
+/*
+ * Launch-plan tuning per L (results never depend on it).
+ *   labs_tune_set / labs_tune_get : the process-wide table used when
+ *     lanes_per_walk / load_factor are 0 (get returns LABS_ENOTFOUND if L has
+ *     no entry, and the built-in default in the outputs).
+ *   labs_autotune : times lanes_per_walk in {2, 4, 8} and load factors
+ *     {0.5, 0.67} on a short run of n_walks x walk_len seeded walks, stores
+ *     the fastest in the table and returns it.  The workspace must hold
+ *     labs_walks_workspace_bytes(L, n_walks, walk_len, lanes 2, load factor
+ *     0.5) plus n_walks * (8W + 12) bytes rounded up to 256 (result buffers of
+ *     the timing runs).  Blocks the calling thread (synchronises `stream`).
+ */
+int32_t labs_tune_set(int32_t L, int32_t lanes_per_walk, double load_factor);
+int32_t labs_tune_get(int32_t L, int32_t *lanes_per_walk, double *load_factor);
+int32_t labs_autotune(int32_t L, int64_t n_walks, int64_t walk_len, void *workspace,
+                      uint64_t ws_bytes, void *stream, int32_t *best_lanes,
+                      double *best_load_factor);
+
+
+/*
+ * Serving: a long-lived server accepts walk requests of any L as they arrive
+ * and runs them with continuous batching.  A scheduler thread admits queued
+ * requests first-come first-served while its device pool has room for their
+ * footprint (visited tables, per-walk progress, outputs), then relaunches the
+ * batch kernel over every admitted request, each launch advancing every
+ * request by up to chunk_steps moves.  Walk state and visited tables stay in
+ * device memory between launches; a request that arrives while others run
+ * joins at the next launch; a finished request's memory is reused at once.
+ * Each request's results equal a standalone labs_walks run with the same
+ * (L, n_walks, walk_len, seed / starts).
+ */
+typedef struct labs_server labs_server;
+
+typedef struct labs_serve_cfg {
+  uint64_t pool_bytes;     /* device pool (allocated once by create); 0 = 50% of free memory */
+  int32_t max_pending;     /* host queue capacity; 0 = 4096 */
+  int32_t lanes_per_walk;  /* 2, 4 or 8; 0 = tuned table / default */
+  int64_t chunk_steps;     /* moves per launch per request; 0 = 8192 */
+  double load_factor;      /* visited-table load factor; 0 = default 0.5 */
+} labs_serve_cfg;
+
+typedef struct labs_serve_result {
+  uint64_t *best_seq;      /* host [n_walks][W] or NULL (caller-owned) */
+  int32_t *best_E;         /* host [n_walks] or NULL */
+  int64_t *steps_done;     /* host [n_walks] or NULL */
+  uint64_t *digest;        /* host [n_walks] or NULL */
+  int64_t t_submit_ns;     /* steady-clock times of submit, first launch, completion */
+  int64_t t_admit_ns;
+  int64_t t_done_ns;
+  int64_t total_steps;     /* sum of steps_done over the request's walks */
+} labs_serve_result;
+
+typedef struct labs_serve_counters {
+  int64_t submitted, admitted, completed, pending, active, launches;
+  int64_t walk_steps;      /* moves made by completed requests */
+  int64_t busy_ns;         /* time the device spent in the server's launches */
+  uint64_t pool_bytes, pool_used, pool_peak;
+} labs_serve_counters;
+
+/* create: allocates the pool and starts the scheduler thread on the current
+ * device.  destroy: stops the thread after the launch in flight, drops
+ * unfinished requests and frees the pool. */
+int32_t labs_serve_create(const labs_serve_cfg *cfg, labs_server **server);
+int32_t labs_serve_destroy(labs_server *server);
+
+/*
+ * submit: queue one request (non-blocking).  starts is a host array
+ * [n_walks][W] that is copied, or NULL for seeded starts.  Returns LABS_EBUSY
+ * when the host queue is full, LABS_EINVAL for invalid arguments or a request
+ * whose footprint exceeds the whole pool.
+ */
+int32_t labs_serve_submit(labs_server *server, int32_t L, int64_t n_walks, int64_t walk_len,
+                          uint64_t seed, const uint64_t *starts, uint64_t *req_id);
+
+/*
+ * poll: LABS_PENDING while the request runs; LABS_OK once done, after copying
+ * its results into the caller's host arrays (the request is then released);
+ * LABS_ENOTFOUND for an unknown or already released id.
+ * wait: like poll but blocks up to timeout_ns (LABS_PENDING on timeout).
+ */
+int32_t labs_serve_poll(labs_server *server, uint64_t req_id, labs_serve_result *res);
+int32_t labs_serve_wait(labs_server *server, uint64_t req_id, int64_t timeout_ns,
+                        labs_serve_result *res);
+int32_t labs_serve_stats(labs_server *server, labs_serve_counters *stats);
 
 #ifdef __cplusplus
 }

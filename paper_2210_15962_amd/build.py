@@ -39,12 +39,13 @@ def build(verbose: bool = True) -> str:
     _run([hipcc, "-x", "hip", f"--offload-arch={ARCH}", *COMMON, *DEVICE_FLAGS, *extra, "-c",
           os.path.join(CSRC, "labs_kernels.hip"), "-o", kern_obj])
     objs.append(kern_obj)
-    api_obj = os.path.join(bdir, "labs_api.o")
-    _run([hipcc, *COMMON, "-D__HIP_PLATFORM_AMD__", "-c", os.path.join(CSRC, "labs_api.cpp"),
-          "-o", api_obj])
-    objs.append(api_obj)
+    for host_src in ("labs_api.cpp", "labs_serve.cpp"):
+        obj = os.path.join(bdir, host_src.replace(".cpp", ".o"))
+        _run([hipcc, *COMMON, "-D__HIP_PLATFORM_AMD__", "-c", os.path.join(CSRC, host_src),
+              "-o", obj])
+        objs.append(obj)
     tmp = LIB + ".tmp"
-    _run([hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp])
+    _run([hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-pthread", "-o", tmp])
     os.replace(tmp, LIB)
     return LIB
 

@@ -231,3 +231,381 @@ int32_t labs_walks(const uint64_t *starts, int32_t L, int64_t n_walks, int64_t w
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Mixed-length batches, their hipGraph form, and the per-L tuning table
+// ---------------------------------------------------------------------------
+#include <map>
+#include <mutex>
+#include <vector>
+
+namespace {
+
+struct Tuned {
+  int32_t lanes;
+  double load_factor;
+};
+
+std::mutex g_tune_mu;
+std::map<int32_t, Tuned> g_tune;
+
+// Built-in choice when L has no tuned entry: four lanes per walk (the fastest
+// setting measured at L = 101 and L = 151 with tens of thousands of walks).
+Tuned tuned_for(int32_t L) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  auto it = g_tune.find(L);
+  if (it != g_tune.end()) return it->second;
+  return Tuned{4, 0.5};
+}
+
+struct BatchPlan {
+  std::vector<lsaw::BatchInstanceDev> inst;
+  std::vector<lsaw::BatchItemDev> items;
+  int variant;
+  uint64_t arena_bytes;
+  uint64_t items_off, inst_off, arena_off;   // byte offsets in the workspace
+};
+
+uint64_t align256(uint64_t x) { return (x + 255) & ~(uint64_t)255; }
+
+int32_t plan_batch(const labs_instance *in, int32_t n_inst, BatchPlan &bp) {
+  if (n_inst < 0) return fail(LABS_EINVAL, "n_inst must be >= 0");
+  if (n_inst > 0 && !in) return fail(LABS_EINVAL, "NULL instance array");
+  bp.inst.clear();
+  bp.items.clear();
+  int nw_max = 1;
+  bp.arena_bytes = 0;
+  struct Ord { int nw, G, L, idx; };
+  std::vector<Ord> order;
+  for (int32_t i = 0; i < n_inst; ++i) {
+    const labs_instance &x = in[i];
+    labs_plan lp{x.lanes_per_walk, x.load_factor, 0};
+    const Tuned tu = tuned_for(x.L);
+    if (lp.lanes_per_walk == 0) lp.lanes_per_walk = tu.lanes;
+    if (lp.load_factor == 0.0) lp.load_factor = tu.load_factor;
+    if (lp.lanes_per_walk != 2 && lp.lanes_per_walk != 4 && lp.lanes_per_walk != 8)
+      return fail(LABS_EINVAL, "instance %d: lanes_per_walk %d (batches use 2, 4 or 8)", i,
+                  lp.lanes_per_walk);
+    Plan p;
+    int32_t rc = make_plan(x.L, x.walk_len, &lp, p);
+    if (rc != LABS_OK) return fail(rc, "instance %d: %s", i, g_err.c_str());
+    if (x.n_walks < 0) return fail(LABS_EINVAL, "instance %d: n_walks < 0", i);
+    if (x.n_walks > 0 && (!x.out.best_seq || !x.out.best_E || !x.out.steps_done))
+      return fail(LABS_EINVAL, "instance %d: best_seq, best_E and steps_done are required", i);
+    if (x.out.n_trace < 0 || x.out.n_trace > x.n_walks)
+      return fail(LABS_EINVAL, "instance %d: n_trace out of range", i);
+    if (x.out.n_trace > 0 && (!x.out.trace_j || !x.out.trace_E))
+      return fail(LABS_EINVAL, "instance %d: trace buffers required", i);
+    lsaw::BatchInstanceDev d{};
+    d.starts = x.starts;
+    d.seed = x.seed;
+    d.walk_len = x.walk_len;
+    d.best_seq = x.out.best_seq;
+    d.best_E = x.out.best_E;
+    d.steps_done = x.out.steps_done;
+    d.digest = x.out.digest;
+    d.trace_j = x.out.trace_j;
+    d.trace_E = x.out.trace_E;
+    d.n_trace = x.out.n_trace;
+    d.table_bytes = p.table_bytes;
+    d.n_buckets = p.n_buckets;
+    d.L = x.L;
+    d.tables = nullptr;
+    d.state = nullptr;
+    d.step_begin = 0;
+    d.step_end = x.walk_len;
+    d.resume = 0;
+    bp.inst.push_back(d);
+    const int nw = lsaw::lag_words_for(x.L);
+    nw_max = std::max(nw_max, nw);
+    const int per_block = lsaw::kBlock / lp.lanes_per_walk;
+    bp.arena_bytes = std::max(bp.arena_bytes, (uint64_t)per_block * p.table_bytes);
+    order.push_back(Ord{nw, lp.lanes_per_walk, x.L, i});
+  }
+  // Items of similar shape run back to back (same code path and table size).
+  std::stable_sort(order.begin(), order.end(), [](const Ord &a, const Ord &b) {
+    if (a.nw != b.nw) return a.nw < b.nw;
+    if (a.G != b.G) return a.G < b.G;
+    return a.L < b.L;
+  });
+  for (const Ord &o : order) {
+    const int per_block = lsaw::kBlock / o.G;
+    const int64_t n = in[o.idx].n_walks;
+    for (int64_t b = 0; b < n; b += per_block) {
+      lsaw::BatchItemDev it{};
+      it.inst = o.idx;
+      it.code = (o.nw << 4) | o.G;
+      it.n_walks = (int32_t)std::min<int64_t>(per_block, n - b);
+      it.walk_begin = b;
+      bp.items.push_back(it);
+    }
+  }
+  bp.variant = lsaw::batch_variant(nw_max);
+  bp.items_off = 256;
+  bp.inst_off = align256(bp.items_off + bp.items.size() * sizeof(lsaw::BatchItemDev));
+  bp.arena_off = align256(bp.inst_off + bp.inst.size() * sizeof(lsaw::BatchInstanceDev));
+  return LABS_OK;
+}
+
+int32_t device_resident_blocks(int variant, int64_t *blocks) {
+  int dev = 0, cus = 0, per_cu = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e == hipSuccess) e = lsaw::batch_blocks_per_cu(variant, &per_cu);
+  if (e != hipSuccess) return fail(LABS_EDEVICE, "device query: %s", hipGetErrorString(e));
+  *blocks = (int64_t)std::max(1, per_cu) * (int64_t)cus;
+  return LABS_OK;
+}
+
+int32_t batch_grid(const BatchPlan &bp, uint64_t ws_bytes, int *grid) {
+  int64_t resident = 0;
+  int32_t rc = device_resident_blocks(bp.variant, &resident);
+  if (rc != LABS_OK) return rc;
+  if (ws_bytes < bp.arena_off + bp.arena_bytes)
+    return fail(LABS_EINVAL, "workspace of %llu bytes is below the minimum %llu",
+                (unsigned long long)ws_bytes, (unsigned long long)(bp.arena_off + bp.arena_bytes));
+  const uint64_t fit = (ws_bytes - bp.arena_off) / std::max<uint64_t>(bp.arena_bytes, 1);
+  int64_t g = std::min<int64_t>((int64_t)bp.items.size(), resident);
+  g = std::min<int64_t>(g, (int64_t)fit);
+  *grid = (int)g;
+  return LABS_OK;
+}
+
+lsaw::BatchLaunch batch_launch(const BatchPlan &bp, uint8_t *ws) {
+  lsaw::BatchLaunch b;
+  b.items = reinterpret_cast<const lsaw::BatchItemDev *>(ws + bp.items_off);
+  b.n_items = (int64_t)bp.items.size();
+  b.inst = reinterpret_cast<const lsaw::BatchInstanceDev *>(ws + bp.inst_off);
+  b.counter = reinterpret_cast<uint32_t *>(ws);
+  b.arena = ws + bp.arena_off;
+  b.arena_bytes = bp.arena_bytes;
+  return b;
+}
+
+}  // namespace
+
+struct labs_batch_graph {
+  hipGraph_t graph;
+  hipGraphExec_t exec;
+};
+
+extern "C" {
+
+int32_t labs_batch_workspace_bytes(const labs_instance *inst, int32_t n_inst, uint64_t *bytes) {
+  if (!bytes) return fail(LABS_EINVAL, "NULL bytes");
+  BatchPlan bp;
+  int32_t rc = plan_batch(inst, n_inst, bp);
+  if (rc != LABS_OK) return rc;
+  int64_t resident = 0;
+  rc = device_resident_blocks(bp.variant, &resident);
+  if (rc != LABS_OK) return rc;
+  const int64_t g = std::min<int64_t>((int64_t)bp.items.size(), resident);
+  *bytes = bp.arena_off + (uint64_t)std::max<int64_t>(g, 1) * bp.arena_bytes;
+  return ok();
+}
+
+int32_t labs_walks_batch(const labs_instance *inst, int32_t n_inst, void *workspace,
+                         uint64_t ws_bytes, void *stream) {
+  BatchPlan bp;
+  int32_t rc = plan_batch(inst, n_inst, bp);
+  if (rc != LABS_OK) return rc;
+  if (bp.items.empty()) return ok();
+  if (!workspace) return fail(LABS_EINVAL, "NULL workspace");
+  int grid = 0;
+  rc = batch_grid(bp, ws_bytes, &grid);
+  if (rc != LABS_OK) return rc;
+  uint8_t *ws = static_cast<uint8_t *>(workspace);
+  hipStream_t st = as_stream(stream);
+  hipError_t e = hipMemcpyAsync(ws + bp.items_off, bp.items.data(),
+                                bp.items.size() * sizeof(lsaw::BatchItemDev), hipMemcpyHostToDevice, st);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(ws + bp.inst_off, bp.inst.data(), bp.inst.size() * sizeof(lsaw::BatchInstanceDev),
+                       hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);   // host vectors die on return
+  if (e == hipSuccess) e = lsaw::launch_batch_reset(reinterpret_cast<uint32_t *>(ws), st);
+  if (e == hipSuccess) e = lsaw::launch_batch(batch_launch(bp, ws), bp.variant, grid, st);
+  if (e != hipSuccess) return fail(LABS_EDEVICE, "batch launch: %s", hipGetErrorString(e));
+  return ok();
+}
+
+int32_t labs_batch_graph_create(const labs_instance *inst, int32_t n_inst, void *workspace,
+                                uint64_t ws_bytes, labs_batch_graph **graph) {
+  if (!graph) return fail(LABS_EINVAL, "NULL graph");
+  *graph = nullptr;
+  BatchPlan bp;
+  int32_t rc = plan_batch(inst, n_inst, bp);
+  if (rc != LABS_OK) return rc;
+  if (!workspace) return fail(LABS_EINVAL, "NULL workspace");
+  int grid = 0;
+  if (!bp.items.empty()) {
+    rc = batch_grid(bp, ws_bytes, &grid);
+    if (rc != LABS_OK) return rc;
+  }
+  uint8_t *ws = static_cast<uint8_t *>(workspace);
+  hipError_t e = hipSuccess;
+  if (!bp.items.empty()) {
+    e = hipMemcpy(ws + bp.items_off, bp.items.data(), bp.items.size() * sizeof(lsaw::BatchItemDev),
+                  hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+      e = hipMemcpy(ws + bp.inst_off, bp.inst.data(), bp.inst.size() * sizeof(lsaw::BatchInstanceDev),
+                    hipMemcpyHostToDevice);
+  }
+  hipStream_t cs = nullptr;
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+  labs_batch_graph *g = new labs_batch_graph{nullptr, nullptr};
+  if (e == hipSuccess) e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    hipError_t k = lsaw::launch_batch_reset(reinterpret_cast<uint32_t *>(ws), cs);
+    if (k == hipSuccess && !bp.items.empty()) k = lsaw::launch_batch(batch_launch(bp, ws), bp.variant, grid, cs);
+    e = hipStreamEndCapture(cs, &g->graph);
+    if (e == hipSuccess) e = k;
+  }
+  if (e == hipSuccess) e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+  if (cs) (void)hipStreamDestroy(cs);
+  if (e != hipSuccess) {
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    delete g;
+    return fail(LABS_EDEVICE, "graph capture: %s", hipGetErrorString(e));
+  }
+  *graph = g;
+  return ok();
+}
+
+int32_t labs_batch_graph_launch(labs_batch_graph *graph, void *stream) {
+  if (!graph) return fail(LABS_EINVAL, "NULL graph");
+  hipError_t e = hipGraphLaunch(graph->exec, as_stream(stream));
+  if (e != hipSuccess) return fail(LABS_EDEVICE, "graph launch: %s", hipGetErrorString(e));
+  return ok();
+}
+
+int32_t labs_batch_graph_destroy(labs_batch_graph *graph) {
+  if (!graph) return ok();
+  if (graph->exec) (void)hipGraphExecDestroy(graph->exec);
+  if (graph->graph) (void)hipGraphDestroy(graph->graph);
+  delete graph;
+  return ok();
+}
+
+int32_t labs_tune_set(int32_t L, int32_t lanes_per_walk, double load_factor) {
+  if (!valid_skew_L(L)) return fail(LABS_EINVAL, "L=%d: need odd L with 3 <= L <= %d", L, lsaw::kLMax);
+  if (lanes_per_walk != 1 && lanes_per_walk != 2 && lanes_per_walk != 4 && lanes_per_walk != 8)
+    return fail(LABS_EINVAL, "lanes_per_walk=%d: use 1, 2, 4 or 8", lanes_per_walk);
+  if (!(load_factor > 0.0 && load_factor <= 0.9))
+    return fail(LABS_EINVAL, "load_factor=%g: use a value in (0, 0.9]", load_factor);
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune[L] = Tuned{lanes_per_walk, load_factor};
+  return ok();
+}
+
+int32_t labs_tune_get(int32_t L, int32_t *lanes_per_walk, double *load_factor) {
+  if (!valid_skew_L(L)) return fail(LABS_EINVAL, "L=%d: need odd L with 3 <= L <= %d", L, lsaw::kLMax);
+  bool found;
+  Tuned t;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune.find(L);
+    found = it != g_tune.end();
+    t = found ? it->second : Tuned{4, 0.5};
+  }
+  if (lanes_per_walk) *lanes_per_walk = t.lanes;
+  if (load_factor) *load_factor = t.load_factor;
+  if (!found) {
+    g_err = "no tuned entry";
+    return LABS_ENOTFOUND;
+  }
+  return ok();
+}
+
+int32_t labs_autotune(int32_t L, int64_t n_walks, int64_t walk_len, void *workspace,
+                      uint64_t ws_bytes, void *stream, int32_t *best_lanes, double *best_load_factor) {
+  if (!valid_skew_L(L)) return fail(LABS_EINVAL, "L=%d: need odd L with 3 <= L <= %d", L, lsaw::kLMax);
+  if (n_walks <= 0 || walk_len <= 0) return fail(LABS_EINVAL, "autotune needs n_walks > 0 and walk_len > 0");
+  if (!workspace) return fail(LABS_EINVAL, "NULL workspace");
+  labs_plan base{2, 0.5, 0};
+  uint64_t need = 0;
+  int32_t rc = labs_walks_workspace_bytes(L, n_walks, walk_len, &base, &need);
+  if (rc != LABS_OK) return rc;
+  const int W = lsaw::key_words_for(L);
+  // Result buffers of the timing runs sit at the front of the workspace.
+  const uint64_t res_bytes = align256((uint64_t)n_walks * (8u * W + 12u));
+  if (ws_bytes < need + res_bytes)
+    return fail(LABS_EINVAL, "autotune workspace below %llu bytes", (unsigned long long)(need + res_bytes));
+  hipStream_t st = as_stream(stream);
+  uint8_t *ws = static_cast<uint8_t *>(workspace);
+  uint64_t *best_seq = reinterpret_cast<uint64_t *>(ws);
+  int64_t *steps = reinterpret_cast<int64_t *>(ws + (uint64_t)n_walks * 8u * W);
+  int32_t *best_E = reinterpret_cast<int32_t *>(ws + (uint64_t)n_walks * (8u * W + 8u));
+  void *tables = ws + res_bytes;
+  const uint64_t tables_bytes = ws_bytes - res_bytes;
+  hipError_t e = hipSuccess;
+  hipEvent_t t0 = nullptr, t1 = nullptr;
+  e = hipEventCreate(&t0);
+  if (e == hipSuccess) e = hipEventCreate(&t1);
+  float best_ms = 1e30f;
+  Tuned best{4, 0.5};
+  const int lanes[3] = {2, 4, 8};
+  const double lfs[2] = {0.5, 0.67};
+  for (int li = 0; li < 3 && e == hipSuccess; ++li) {
+    for (int fi = 0; fi < 2 && e == hipSuccess; ++fi) {
+      labs_plan p{lanes[li], lfs[fi], 0};
+      labs_walk_out o{best_seq, best_E, steps, nullptr, nullptr, nullptr, 0};
+      // one untimed run (clock ramp), one timed run
+      for (int rep = 0; rep < 2 && e == hipSuccess; ++rep) {
+        if (rep == 1) e = hipEventRecord(t0, st);
+        if (e != hipSuccess) break;
+        rc = labs_walks(nullptr, L, n_walks, walk_len, 1234 + rep, &o, tables, tables_bytes, &p, stream);
+        if (rc != LABS_OK) { e = hipErrorUnknown; break; }
+        if (rep == 1) e = hipEventRecord(t1, st);
+      }
+      if (e == hipSuccess) e = hipEventSynchronize(t1);
+      float ms = 0.f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, t0, t1);
+      if (e == hipSuccess && ms < best_ms) { best_ms = ms; best = Tuned{lanes[li], lfs[fi]}; }
+    }
+  }
+  if (t0) (void)hipEventDestroy(t0);
+  if (t1) (void)hipEventDestroy(t1);
+  if (e != hipSuccess) return fail(LABS_EDEVICE, "autotune: %s", rc != LABS_OK ? g_err.c_str() : hipGetErrorString(e));
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune[L] = best;
+  }
+  if (best_lanes) *best_lanes = best.lanes;
+  if (best_load_factor) *best_load_factor = best.load_factor;
+  return ok();
+}
+
+}  // extern "C"
+
+namespace lsaw {
+
+int32_t set_error(int32_t code, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+int32_t clear_error() { return ok(); }
+
+bool table_geometry(int32_t L, int64_t walk_len, double load_factor, uint32_t *n_buckets,
+                    uint64_t *table_bytes) {
+  labs_plan lp{2, load_factor, 0};
+  Plan p;
+  if (make_plan(L, walk_len, &lp, p) != LABS_OK) return false;
+  *n_buckets = p.n_buckets;
+  *table_bytes = p.table_bytes;
+  return true;
+}
+
+void tuned_plan(int32_t L, int32_t *lanes, double *load_factor) {
+  const Tuned t = tuned_for(L);
+  *lanes = t.lanes;
+  *load_factor = t.load_factor;
+}
+
+}  // namespace lsaw

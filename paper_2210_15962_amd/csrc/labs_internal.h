@@ -38,6 +38,71 @@ struct WalkLaunch {
   int32_t lanes_per_walk;   // 1, 2, 4 or 8
 };
 
+// Progress of one walk between launches (continuous batching): the pivot, the
+// best so far, the digest chain, moves made, the predecessor and a stop flag.
+struct WalkState {
+  uint64_t P[3];
+  uint64_t bestP[3];
+  uint64_t h;
+  int64_t steps;
+  int32_t bestE;
+  uint32_t prev_jm1;
+  uint32_t trapped;
+  uint32_t pad;
+};
+
+// Mixed-length batches: one persistent launch drains a device work queue of
+// (instance, block of walks) items.
+struct BatchInstanceDev {
+  const uint64_t *starts;
+  uint64_t seed;
+  int64_t walk_len;
+  uint64_t *best_seq;
+  int32_t *best_E;
+  int64_t *steps_done;
+  uint64_t *digest;
+  int16_t *trace_j;
+  int32_t *trace_E;
+  int64_t n_trace;
+  uint64_t table_bytes;
+  uint32_t n_buckets;
+  int32_t L;
+  uint8_t *tables;          // per-walk tables (walk w at + w*table_bytes), or
+                            // nullptr: the workgroup's arena, cleared per item
+  WalkState *state;         // per-walk progress, or nullptr (single launch)
+  int64_t step_begin;       // moves made by every still-moving walk so far
+  int64_t step_end;         // stop when a walk has made this many moves
+  int32_t resume;           // 1: continue from state (tables already filled)
+  int32_t pad;
+};
+
+struct BatchItemDev {
+  int32_t inst;       // instance index
+  int32_t code;       // (lag words << 4) | lanes per walk
+  int32_t n_walks;    // walks of this block
+  int32_t pad;
+  int64_t walk_begin; // first walk of the block within its instance
+};
+
+struct BatchLaunch {
+  const BatchItemDev *items;
+  int64_t n_items;
+  const BatchInstanceDev *inst;
+  uint32_t *counter;      // work-queue head, zeroed by launch_batch_reset
+  uint8_t *arena;         // visited tables: arena_bytes per resident workgroup
+  uint64_t arena_bytes;
+};
+
+// Host helpers shared by labs_api.cpp and labs_serve.cpp.
+int32_t set_error(int32_t code, const char *fmt, ...);
+int32_t clear_error();
+// Visited-table geometry for walk_len moves at a load factor (false if the
+// table would not fit 32-bit bucket indices).
+bool table_geometry(int32_t L, int64_t walk_len, double load_factor, uint32_t *n_buckets,
+                    uint64_t *table_bytes);
+// Lanes per walk and load factor from the tuning table (or the default).
+void tuned_plan(int32_t L, int32_t *lanes, double *load_factor);
+
 // Device entry points (labs_kernels.hip).  Return hipSuccess or the launch error.
 hipError_t launch_energy(const int8_t *seqs, int32_t L, int64_t n, int32_t *E_out,
                          hipStream_t stream);
@@ -46,5 +111,11 @@ hipError_t launch_starts(int32_t L, int64_t n_walks, uint64_t seed, uint64_t *ou
 hipError_t launch_walks(const WalkLaunch &w, hipStream_t stream);
 // Dynamic LDS bytes the walk kernel needs for length L (0 if unsupported).
 size_t walk_lds_bytes(int32_t L);
+// Batch kernel variant able to run lag-word classes up to nw_max (2, 4 or 6).
+int batch_variant(int nw_max);
+size_t batch_lds_bytes(int variant);
+hipError_t batch_blocks_per_cu(int variant, int *blocks);
+hipError_t launch_batch_reset(uint32_t *counter, hipStream_t stream);
+hipError_t launch_batch(const BatchLaunch &b, int variant, int grid, hipStream_t stream);
 
 }  // namespace lsaw

@@ -59,7 +59,16 @@ __device__ __forceinline__ uint64_t mix64(uint64_t z) {
 }
 
 __device__ __forceinline__ uint32_t popc_add(uint32_t x, uint32_t acc) {
-  return (uint32_t)__builtin_popcount(x) + acc;
+  uint32_t r;
+  asm("v_bcnt_u32_b32 %0, %1, %2" : "=v"(r) : "v"(x), "v"(acc));
+  return r;
+}
+
+// Median of three unsigned values (one v_med3_u32).
+__device__ __forceinline__ uint32_t umed3(uint32_t a, uint32_t b, uint32_t c) {
+  uint32_t r;
+  asm("v_med3_u32 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+  return r;
 }
 
 __device__ __forceinline__ uint32_t funnel(uint32_t hi, uint32_t lo, uint32_t sh) {
@@ -80,6 +89,29 @@ __device__ __forceinline__ uint32_t group_max(uint32_t v) {
   if constexpr (G >= 4) v = max(v, (uint32_t)__builtin_amdgcn_ds_swizzle((int)v, 0x081F));
   if constexpr (G >= 8) v = max(v, (uint32_t)__builtin_amdgcn_ds_swizzle((int)v, 0x101F));
   return v;
+}
+// Same with the group size known only at run time (G == 0), wave-uniform Gl.
+template <int G>
+__device__ __forceinline__ uint32_t grp_min(uint32_t v, int Gl) {
+  if constexpr (G > 0) {
+    return group_min<G>(v);
+  } else {
+    if (Gl >= 2) v = min(v, (uint32_t)__builtin_amdgcn_ds_swizzle((int)v, 0x041F));
+    if (Gl >= 4) v = min(v, (uint32_t)__builtin_amdgcn_ds_swizzle((int)v, 0x081F));
+    if (Gl >= 8) v = min(v, (uint32_t)__builtin_amdgcn_ds_swizzle((int)v, 0x101F));
+    return v;
+  }
+}
+template <int G>
+__device__ __forceinline__ uint32_t grp_max(uint32_t v, int Gl) {
+  if constexpr (G > 0) {
+    return group_max<G>(v);
+  } else {
+    if (Gl >= 2) v = max(v, (uint32_t)__builtin_amdgcn_ds_swizzle((int)v, 0x041F));
+    if (Gl >= 4) v = max(v, (uint32_t)__builtin_amdgcn_ds_swizzle((int)v, 0x081F));
+    if (Gl >= 8) v = max(v, (uint32_t)__builtin_amdgcn_ds_swizzle((int)v, 0x101F));
+    return v;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -200,40 +232,57 @@ struct CandVec {
   uint32_t jm1;
 };
 
+// Loads candidate j's descriptor row and neighbour vectors.  Only the first
+// FW forward and BW backward lag words are formed; the caller guarantees every
+// later word has an all-zero mask for this candidate (FW, BW wave-uniform).
 template <int NW>
 __device__ __forceinline__ void load_candidate(const uint32_t *desc_row, const uint8_t *lds,
-                                               uint32_t colbase, CandVec<NW> &cv) {
+                                               uint32_t colbase, CandVec<NW> &cv, int FW, int BW) {
   using Gm = Geom<NW>;
   const uint4 d0 = *reinterpret_cast<const uint4 *>(desc_row);
   const uint4 d1 = *reinterpret_cast<const uint4 *>(desc_row + 4);
   cv.kc = (int32_t)d1.z;
   cv.N = (int32_t)d1.w;
   cv.jm1 = desc_row[DS_JM1];
-#pragma unroll
-  for (int w = 0; w < NW; ++w) cv.mf[w] = desc_row[DS_MASKS + w];
-#pragma unroll
-  for (int w = 0; w < Gm::NWB; ++w) {
-    cv.mb[w] = desc_row[DS_MASKS + NW + w];
-    cv.mfb[w] = desc_row[DS_MASKS + NW + Gm::NWB + w];
-  }
   const uint32_t *fsrc = reinterpret_cast<const uint32_t *>(lds + colbase + d0.x);
   const uint32_t *bsrc = reinterpret_cast<const uint32_t *>(lds + colbase + d0.z);
-  uint32_t fs[NW + 1], bs[Gm::NWB + 1];
-#pragma unroll
-  for (int w = 0; w <= NW; ++w) fs[w] = fsrc[w * kBlock];
-#pragma unroll
-  for (int w = 0; w <= Gm::NWB; ++w) bs[w] = bsrc[w * kBlock];
   const uint32_t sw = *reinterpret_cast<const uint32_t *>(lds + colbase + d1.x);
+  uint32_t lo = fsrc[0];
 #pragma unroll
-  for (int w = 0; w < NW; ++w) cv.fw[w] = funnel(fs[w + 1], fs[w], d0.y);
+  for (int w = 0; w < NW; ++w) {
+    if (w < FW) {
+      cv.mf[w] = desc_row[DS_MASKS + w];
+      const uint32_t hi = fsrc[(w + 1) * kBlock];
+      cv.fw[w] = funnel(hi, lo, d0.y);
+      lo = hi;
+    } else {
+      cv.mf[w] = 0u;
+      cv.fw[w] = 0u;
+    }
+  }
+  uint32_t blo = bsrc[0];
 #pragma unroll
-  for (int w = 0; w < Gm::NWB; ++w) cv.bw[w] = funnel(bs[w + 1], bs[w], d0.w);
+  for (int w = 0; w < Gm::NWB; ++w) {
+    if (w < BW) {
+      cv.mb[w] = desc_row[DS_MASKS + NW + w];
+      cv.mfb[w] = desc_row[DS_MASKS + NW + Gm::NWB + w];
+      const uint32_t hi = bsrc[(w + 1) * kBlock];
+      cv.bw[w] = funnel(hi, blo, d0.w);
+      blo = hi;
+    } else {
+      cv.mb[w] = 0u;
+      cv.mfb[w] = 0u;
+      cv.bw[w] = 0u;
+    }
+  }
   cv.sbit = (sw >> d1.y) & 1u;
 }
 
 // Candidate key: ((dE/8 + kBias) << 8) | (j-1).  Unsigned order = (dE, j) order.
+// Words at or beyond FW (forward) / BW (backward) are skipped (wave-uniform).
 template <int NW>
-__device__ __forceinline__ uint32_t candidate_key(const CandVec<NW> &cv, const uint32_t *P) {
+__device__ __forceinline__ uint32_t candidate_key(const CandVec<NW> &cv, const uint32_t *P,
+                                                  int FW, int BW) {
   using Gm = Geom<NW>;
   constexpr int BM = Gm::BMAX;
   uint32_t cnt[BM - 1];
@@ -243,16 +292,20 @@ __device__ __forceinline__ uint32_t candidate_key(const CandVec<NW> &cv, const u
   static_for<0, NW>([&](auto wc) {
     constexpr int w = decltype(wc)::value;
     constexpr int Bw = planes_of(NW, w), off = plane_off(NW, w);
-    uint32_t s = 0;
+    if (w < FW) {
+      uint32_t s = 0;
 #pragma unroll
-    for (int b = 0; b < Bw - 1; ++b) cnt[b] = popc_add((P[off + b] ^ cv.fw[w]) & cv.mf[w], cnt[b]);
-    s = popc_add((P[off + Bw - 1] ^ cv.fw[w]) & cv.mf[w], s);
-    if constexpr (w < Gm::NWB) {
+      for (int b = 0; b < Bw - 1; ++b) cnt[b] = popc_add((P[off + b] ^ cv.fw[w]) & cv.mf[w], cnt[b]);
+      s = popc_add((P[off + Bw - 1] ^ cv.fw[w]) & cv.mf[w], s);
+      if constexpr (w < Gm::NWB) {
+        if (w < BW) {
 #pragma unroll
-      for (int b = 0; b < Bw - 1; ++b) cnt[b] = popc_add((P[off + b] ^ cv.bw[w]) & cv.mb[w], cnt[b]);
-      s = popc_add((P[off + Bw - 1] ^ cv.bw[w]) & cv.mb[w], s);
+          for (int b = 0; b < Bw - 1; ++b) cnt[b] = popc_add((P[off + b] ^ cv.bw[w]) & cv.mb[w], cnt[b]);
+          s = popc_add((P[off + Bw - 1] ^ cv.bw[w]) & cv.mb[w], s);
+        }
+      }
+      X -= (int32_t)(s << (Bw - 1));   // sign plane of this word
     }
-    X -= (int32_t)(s << (Bw - 1));   // sign plane of this word
   });
   // X += sum_b 2^b cnt_b  (Horner), giving sum over masked lags of (c_t XOR -f_t).
   int32_t Hn = (int32_t)cnt[BM - 2];
@@ -261,11 +314,36 @@ __device__ __forceinline__ uint32_t candidate_key(const CandVec<NW> &cv, const u
   X += Hn;
   uint32_t q = 0;
 #pragma unroll
-  for (int w = 0; w < Gm::NWB; ++w) q = popc_add((cv.fw[w] ^ cv.bw[w]) & cv.mfb[w], q);
+  for (int w = 0; w < Gm::NWB; ++w)
+    if (w < BW) q = popc_add((cv.fw[w] ^ cv.bw[w]) & cv.mfb[w], q);
   const int32_t Y = 2 * X + cv.N;
   const int32_t Z = cv.kc - 8 * (int32_t)q;
   const int32_t val = cv.sbit ? Z + Y : Z - Y;
   return ((uint32_t)val << 8) | cv.jm1;
+}
+
+// Lag words some candidate of iteration i (j = G*i + 1 .. G*i + G) needs:
+// forward words cover the largest forward range (smallest j of either class),
+// backward words the largest backward range (largest j).
+template <int NW>
+__device__ __forceinline__ void iteration_words(int i, int D, int G, int &FW, int &BW) {
+  using Gm = Geom<NW>;
+  const int m = D - 1;
+  const int jlo = G * i + 1;
+  const int jhi = min(G * i + G, D);
+  auto nF = [&](int j) -> int {
+    if (j >= D) return 0;
+    const int nc = (j & 1) ? D : m;
+    return nc - 1 - ((j - 1) >> 1);
+  };
+  int f = nF(jlo);
+  if (jlo + 1 <= D) f = max(f, nF(jlo + 1));
+  const int b = (jhi - 1) >> 1;
+  BW = min(Gm::NWB, (b + 31) >> 5);
+  // The per-word loop of candidate_key visits w < FW and nests the backward
+  // planes inside it, so FW must cover BW (the centre j = D alone has no
+  // forward lags but still has backward ones).
+  FW = max(min(NW, (f + 31) >> 5), BW);
 }
 
 // c_t += 2u_t on the bit planes for the move j (u from the pre-move vectors):
@@ -384,27 +462,50 @@ __device__ __forceinline__ void topk_insert(uint32_t (&tk)[K], uint32_t x) {
   } else {
     // Sorted insertion: new[i] = median(old[i-1], old[i], x), new[0] = min.
 #pragma unroll
-    for (int i = K - 1; i >= 1; --i) tk[i] = max(tk[i - 1], min(tk[i], x));  // tk sorted: median
+    for (int i = K - 1; i >= 1; --i) tk[i] = umed3(tk[i - 1], tk[i], x);   // tk sorted
     tk[0] = min(tk[0], x);
   }
 }
 
+// One workgroup's share of a walk batch: up to kBlock/G walks of one length L.
+struct BlockTask {
+  const uint64_t *starts;   // first pivots of the walks' instance, or nullptr
+  uint64_t seed;            // seeded starts: SplitMix64 of (seed, walk index)
+  int32_t L;
+  int32_t n_walks;          // walks of this block (<= kBlock / lanes)
+  int32_t lanes;            // lanes per walk (1, 2, 4 or 8)
+  int64_t walk_begin;       // index of the block's first walk within its instance
+  int64_t walk_len;
+  uint64_t *best_seq;
+  int32_t *best_E;
+  int64_t *steps_done;
+  uint64_t *digest;
+  int16_t *trace_j;
+  int32_t *trace_E;
+  int64_t n_trace;
+  uint8_t *tables;          // visited table of slot s at tables + s * table_bytes
+  uint64_t table_bytes;
+  uint32_t n_buckets;
+  WalkState *state;         // per-walk progress (indexed by walk) or nullptr
+  int64_t step_begin;       // moves every still-moving walk has made so far
+  int64_t step_end;         // moves after which this launch stops a walk
+  int32_t resume;           // continue from state: no clear, no P_1 insert
+};
+
 template <int NW, int G, int K>
-__global__ void __launch_bounds__(kBlock) walk_kernel(const WalkLaunch a) {
+__device__ __forceinline__ void run_block(const BlockTask &a, uint8_t *lds) {
   using Gm = Geom<NW>;
-  extern __shared__ __align__(16) uint8_t lds[];
+  const int Gl = (G > 0) ? G : a.lanes;        // lanes per walk (wave-uniform)
   uint32_t *desc = reinterpret_cast<uint32_t *>(lds);
   uint8_t *cols = lds + (size_t)Gm::DMAX * Gm::DESC * 4;
 
   const int L = a.L, D = (L + 1) / 2, m = (L - 1) / 2;
   const int KW = (D + 63) / 64;
   build_descriptors<NW>(desc, L);
-  {
+  if (!a.resume) {
     // Clear the visited tables of this block's walks (contiguous, coalesced).
-    const int64_t first = (int64_t)blockIdx.x * (kBlock / G);
-    const int64_t nwb = min((int64_t)(kBlock / G), a.n_walks - first);
-    uint4 *p = reinterpret_cast<uint4 *>(a.tables + (uint64_t)first * a.table_bytes);
-    const uint64_t n16 = (uint64_t)nwb * (a.table_bytes / 16u);
+    uint4 *p = reinterpret_cast<uint4 *>(a.tables);
+    const uint64_t n16 = (uint64_t)a.n_walks * (a.table_bytes / 16u);
     const uint4 z = {0u, 0u, 0u, 0u};
 #pragma unroll 4
     for (uint64_t i = threadIdx.x; i < n16; i += kBlock) p[i] = z;
@@ -412,17 +513,23 @@ __global__ void __launch_bounds__(kBlock) walk_kernel(const WalkLaunch a) {
   __syncthreads();
 
   const int tid = (int)threadIdx.x;
-  const int r = tid % G;                       // lane rank inside the walk group
-  const int64_t local = (int64_t)blockIdx.x * (kBlock / G) + tid / G;
-  const int64_t walk = a.walk_begin + local;
-  bool active = local < a.n_walks;
+  const int r = tid % Gl;                       // lane rank inside the walk group
+  const int slot = tid / Gl;                    // walk slot inside the block
+  const int64_t walk = a.walk_begin + slot;
+  bool active = slot < a.n_walks;
   const uint32_t colbase = (uint32_t)tid * 4u;
   uint32_t *colw = reinterpret_cast<uint32_t *>(cols);
   const bool e32 = D > 127;
 
-  // ---- first pivot P_1 ---------------------------------------------------
+  // ---- first pivot P_1, or the pivot reached by an earlier launch ----------
   Key3 P{0, 0, 0};
-  if (active) {
+  WalkState ws{};
+  if (active && a.resume) {
+    ws = a.state[walk];
+    P.w0 = ws.P[0];
+    P.w1 = ws.P[1];
+    P.w2 = ws.P[2];
+  } else if (active) {
     auto start_word = [&](int t) -> uint64_t {
       if (t >= KW) return 0ull;
       uint64_t v;
@@ -498,18 +605,32 @@ __global__ void __launch_bounds__(kBlock) walk_kernel(const WalkLaunch a) {
   uint64_t h = 0;
   int64_t steps = 0;
   uint32_t prev_jm1 = 0xFFFFFFFFu;
-  uint8_t *table = a.tables + (uint64_t)(active ? local : 0) * a.table_bytes;
+  bool trapped = false;
+  uint8_t *table = a.tables + (uint64_t)(active ? slot : 0) * a.table_bytes;
+  if (active && a.resume) {
+    bestE = ws.bestE;
+    bestP = Key3{ws.bestP[0], ws.bestP[1], ws.bestP[2]};
+    h = ws.h;
+    steps = ws.steps;
+    prev_jm1 = ws.prev_jm1;
+    trapped = ws.trapped != 0u;
+    if (trapped) active = false;
+  }
 
   // Insert P_1 (the table is empty: first entry of its home bucket).
-  if (active && r == 0) store_entry(table + (uint64_t)bucket_of(P, a.n_buckets) * kBucketBytes, P, e32);
+  if (active && !a.resume && r == 0)
+    store_entry(table + (uint64_t)bucket_of(P, a.n_buckets) * kBucketBytes, P, e32);
 
-  // Local candidates of lane r: j = r + 1 + G*i.
-  const int ncand = (D - r + G - 1) / G;       // may be 0 for r >= D
+  // Local candidates of lane r: j = r + 1 + Gl*i.
+  const int ncand = (D - r + Gl - 1) / Gl;       // may be 0 for r >= D
   const bool tracing = active && walk < a.n_trace;
 
-  for (int64_t step = 0; step < a.walk_len; ++step) {
+  // Every walk still moving has made exactly step_begin moves (trapped walks
+  // are inactive), so the step counter is uniform across the workgroup.
+  const int64_t step_stop = min(a.step_end, a.walk_len);
+  for (int64_t step = a.step_begin; step < step_stop; ++step) {
     if (__ballot(active) == 0ull) break;
-    // Excluded local candidates (bit i <-> j = r + 1 + G*i): the predecessor,
+    // Excluded local candidates (bit i <-> j = r + 1 + Gl*i): the predecessor,
     // then every candidate found visited during this step.
     uint64_t ex0 = 0ull, ex1 = 0ull, ex2 = 0ull;
     auto exclude = [&](uint32_t li) {
@@ -519,7 +640,7 @@ __global__ void __launch_bounds__(kBlock) walk_kernel(const WalkLaunch a) {
       ex1 |= (q == 1u) ? bit : 0ull;
       ex2 |= (q == 2u) ? bit : 0ull;
     };
-    if (prev_jm1 != 0xFFFFFFFFu && (int)(prev_jm1 % G) == r) exclude(prev_jm1 / G);
+    if (prev_jm1 != 0xFFFFFFFFu && (int)(prev_jm1 % Gl) == r) exclude(prev_jm1 / Gl);
 
     uint32_t tk[K];
     bool lane_empty = false;      // no non-excluded local candidate is left
@@ -528,27 +649,59 @@ __global__ void __launch_bounds__(kBlock) walk_kernel(const WalkLaunch a) {
     bool pstarted = false;
     uint32_t pbucket = 0, pslot = 0;
     Key3 pkey{0, 0, 0};
-    bool need_scan = true;
+    bool need_scan = false;
     bool done = !active;
     uint32_t win = kKeyMax;
 
+    const int nmax = (D + Gl - 1) / Gl;
+    // (0) main scan: every local candidate goes into the top-K.
+#pragma unroll
+    for (int i = 0; i < K; ++i) tk[i] = kKeyMax;
+#pragma unroll 1
+    for (int i = 0; i < nmax; ++i) {
+      int FW, BW;
+      iteration_words<NW>(i, D, Gl, FW, BW);
+      const bool live = i < ncand;
+      const int j = live ? (r + 1 + Gl * i) : 1;
+      CandVec<NW> cv;
+      load_candidate<NW>(desc + (j - 1) * Gm::DESC, cols, colbase, cv, FW, BW);
+      const uint32_t key = candidate_key<NW>(cv, Pl, FW, BW);
+      if (live) topk_insert<K>(tk, key);
+    }
+    // The predecessor is visited: drop it from its owner's top-K.
+    if (prev_jm1 != 0xFFFFFFFFu && (int)(prev_jm1 % Gl) == r) {
+      bool found = false;
+#pragma unroll
+      for (int i = 0; i < K; ++i) {
+        found = found || (tk[i] != kKeyMax && (tk[i] & 0xFFu) == prev_jm1);
+        if (found) tk[i] = (i + 1 < K) ? tk[i + 1 < K ? i + 1 : i] : kKeyMax;
+      }
+      // Counts as a pop: after K removals the lane must rescan, while an
+      // empty head before that means every local candidate was examined.
+      npop = found ? 1 : 0;
+    }
+    need_scan = false;
+    lane_empty = tk[0] == kKeyMax;
+
     for (;;) {
-      // (1) scan / rescan of local candidates, skipping excluded ones.
+      // (1) rescan of local candidates, skipping excluded ones (a lane whose
+      //     top-K entries were all found visited).
       if (__ballot(!done && need_scan) != 0ull) {
         if (!done && need_scan) {
 #pragma unroll
           for (int i = 0; i < K; ++i) tk[i] = kKeyMax;
         }
-        const int nmax = (D + G - 1) / G;
         uint64_t xw = 0ull;
 #pragma unroll 1
         for (int i = 0; i < nmax; ++i) {
           if ((i & 63) == 0) xw = (i < 64) ? ex0 : (i < 128) ? ex1 : ex2;
+          int FW, BW;
+          iteration_words<NW>(i, D, Gl, FW, BW);
           const bool live = !done && need_scan && i < ncand;
-          const int j = live ? (r + 1 + G * i) : 1;
+          const int j = live ? (r + 1 + Gl * i) : 1;
           CandVec<NW> cv;
-          load_candidate<NW>(desc + (j - 1) * Gm::DESC, cols, colbase, cv);
-          uint32_t key = candidate_key<NW>(cv, Pl);
+          load_candidate<NW>(desc + (j - 1) * Gm::DESC, cols, colbase, cv, FW, BW);
+          uint32_t key = candidate_key<NW>(cv, Pl, FW, BW);
           key |= 0u - (uint32_t)(xw & 1ull);
           xw >>= 1;
           if (live) topk_insert<K>(tk, key);
@@ -584,10 +737,10 @@ __global__ void __launch_bounds__(kBlock) walk_kernel(const WalkLaunch a) {
       }
       // (3) merge the heads of the group.
       const uint32_t my = head_valid ? head : kKeyMax;
-      const uint32_t gmin = group_min<G>(my);
+      const uint32_t gmin = grp_min<G>(my, Gl);
       const bool owner = head_valid && my == gmin;
-      const uint32_t ostat = group_max<G>(owner ? (uint32_t)(hstat + 1) : 0u);
-      const bool exhausted_any = group_max<G>((!done && !lane_empty && npop >= K) ? 1u : 0u) != 0u;
+      const uint32_t ostat = grp_max<G>(owner ? (uint32_t)(hstat + 1) : 0u, Gl);
+      const bool exhausted_any = grp_max<G>((!done && !lane_empty && npop >= K) ? 1u : 0u, Gl) != 0u;
       if (!done) {
         if (exhausted_any) {
           // some lane must refill its top-K before the group can decide
@@ -599,7 +752,7 @@ __global__ void __launch_bounds__(kBlock) walk_kernel(const WalkLaunch a) {
           win = gmin;
         } else if (ostat == 3u) {
           if (owner) {
-            exclude((head & 0xFFu) / G);
+            exclude((head & 0xFFu) / Gl);
 #pragma unroll
             for (int i = 0; i + 1 < K; ++i) tk[i] = tk[i + 1];
             tk[K - 1] = kKeyMax;
@@ -617,11 +770,12 @@ __global__ void __launch_bounds__(kBlock) walk_kernel(const WalkLaunch a) {
     if (active) {
       if (win == kKeyMax) {
         active = false;         // trapped walk stops here
+        trapped = true;
       } else {
         const uint32_t jm1 = win & 0xFFu;
         const int32_t dE = 8 * ((int32_t)(win >> 8) - kBias);
         CandVec<NW> cv;
-        load_candidate<NW>(desc + jm1 * Gm::DESC, cols, colbase, cv);
+        load_candidate<NW>(desc + jm1 * Gm::DESC, cols, colbase, cv, NW, Gm::NWB);
         apply_move_planes<NW>(cv, Pl);
         // flip sequence positions j and L+1-j (same class) in all arrays
         const int j = (int)jm1 + 1;
@@ -655,7 +809,19 @@ __global__ void __launch_bounds__(kBlock) walk_kernel(const WalkLaunch a) {
     }
   }
 
-  if (local < a.n_walks && r == 0) {
+  const bool finished = trapped || steps >= a.walk_len;
+  if (a.state && slot < a.n_walks && r == 0) {
+    WalkState o{};
+    o.P[0] = P.w0; o.P[1] = P.w1; o.P[2] = P.w2;
+    o.bestP[0] = bestP.w0; o.bestP[1] = bestP.w1; o.bestP[2] = bestP.w2;
+    o.h = h;
+    o.steps = steps;
+    o.bestE = bestE;
+    o.prev_jm1 = prev_jm1;
+    o.trapped = trapped ? 1u : 0u;
+    a.state[walk] = o;
+  }
+  if (finished && slot < a.n_walks && r == 0) {
     a.best_seq[walk * KW] = bestP.w0;
     if (KW > 1) a.best_seq[walk * KW + 1] = bestP.w1;
     if (KW > 2) a.best_seq[walk * KW + 2] = bestP.w2;
@@ -663,6 +829,87 @@ __global__ void __launch_bounds__(kBlock) walk_kernel(const WalkLaunch a) {
     a.steps_done[walk] = steps;
     if (a.digest) a.digest[walk] = mix64(h ^ (uint64_t)steps);
   }
+}
+
+template <int NW, int G, int K>
+__global__ void __launch_bounds__(kBlock) walk_kernel(const WalkLaunch w) {
+  extern __shared__ __align__(16) uint8_t lds[];
+  const int64_t first = (int64_t)blockIdx.x * (kBlock / G);
+  BlockTask t;
+  t.starts = w.starts;
+  t.seed = w.seed;
+  t.L = w.L;
+  t.n_walks = (int32_t)min((int64_t)(kBlock / G), w.n_walks - first);
+  t.lanes = G;
+  t.walk_begin = w.walk_begin + first;
+  t.walk_len = w.walk_len;
+  t.best_seq = w.best_seq;
+  t.best_E = w.best_E;
+  t.steps_done = w.steps_done;
+  t.digest = w.digest;
+  t.trace_j = w.trace_j;
+  t.trace_E = w.trace_E;
+  t.n_trace = w.n_trace;
+  t.tables = w.tables + (uint64_t)first * w.table_bytes;
+  t.table_bytes = w.table_bytes;
+  t.n_buckets = w.n_buckets;
+  t.state = nullptr;
+  t.step_begin = 0;
+  t.step_end = w.walk_len;
+  t.resume = 0;
+  run_block<NW, G, K>(t, lds);
+}
+
+// ---------------------------------------------------------------------------
+// Persistent mixed-length batch kernel: every workgroup takes (instance, block)
+// items from a device counter until the queue is empty, running each item with
+// the variant compiled for its lag-word class and lanes per walk.
+// ---------------------------------------------------------------------------
+
+template <int NWMAX>
+__global__ void __launch_bounds__(kBlock) batch_kernel(const BatchLaunch b) {
+  extern __shared__ __align__(16) uint8_t lds[];
+  __shared__ int64_t s_item;
+  uint8_t *arena = b.arena + (uint64_t)blockIdx.x * b.arena_bytes;
+  for (;;) {
+    __syncthreads();                       // previous item finished, s_item consumed
+    if (threadIdx.x == 0) s_item = (int64_t)atomicAdd(b.counter, 1u);
+    __syncthreads();
+    const int64_t it = s_item;
+    if (it >= b.n_items) break;            // uniform: every wave leaves together
+    const BatchItemDev item = b.items[it];
+    const BatchInstanceDev &in = b.inst[item.inst];
+    BlockTask t;
+    t.starts = in.starts;
+    t.seed = in.seed;
+    t.L = in.L;
+    t.n_walks = item.n_walks;
+    t.walk_begin = item.walk_begin;
+    t.walk_len = in.walk_len;
+    t.best_seq = in.best_seq;
+    t.best_E = in.best_E;
+    t.steps_done = in.steps_done;
+    t.digest = in.digest;
+    t.trace_j = in.trace_j;
+    t.trace_E = in.trace_E;
+    t.n_trace = in.n_trace;
+    t.tables = in.tables ? in.tables + (uint64_t)item.walk_begin * in.table_bytes : arena;
+    t.table_bytes = in.table_bytes;
+    t.n_buckets = in.n_buckets;
+    t.state = in.state;
+    t.step_begin = in.step_begin;
+    t.step_end = in.step_end;
+    t.resume = in.resume;
+    t.lanes = item.code & 15;
+    // Compiled for the largest lag-word class of the batch: shorter lengths
+    // skip the unused lag words (uniform guards), lanes per walk is a runtime
+    // value, so one code path serves every item.
+    run_block<NWMAX, 0, 3>(t, lds);
+  }
+}
+
+__global__ void batch_reset_kernel(uint32_t *counter) {
+  if (threadIdx.x == 0) *counter = 0u;
 }
 
 // ---------------------------------------------------------------------------
@@ -766,7 +1013,7 @@ size_t walk_lds_bytes(int32_t L) {
 
 template <int NW, int G>
 static hipError_t launch_nw_g(const WalkLaunch &w, hipStream_t stream) {
-  constexpr int K = (G == 1) ? 4 : 2;
+  constexpr int K = (G == 1) ? 4 : 3;
   const size_t lds = Geom<NW>::lds_bytes();
   auto kern = walk_kernel<NW, G, K>;
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
@@ -799,6 +1046,60 @@ hipError_t launch_walks(const WalkLaunch &w, hipStream_t stream) {
     case 5: return launch_nw<5>(w, stream);
     case 6: return launch_nw<6>(w, stream);
     default: return hipErrorInvalidValue;
+  }
+}
+
+
+int batch_variant(int nw_max) { return nw_max <= 2 ? 2 : (nw_max <= 4 ? 4 : 6); }
+
+size_t batch_lds_bytes(int variant) {
+  switch (variant) {
+    case 2: return lds_for<2>();
+    case 4: return lds_for<4>();
+    default: return lds_for<6>();
+  }
+}
+
+template <int V>
+static const void *batch_fn() { return reinterpret_cast<const void *>(batch_kernel<V>); }
+
+static const void *batch_kernel_ptr(int variant) {
+  switch (variant) {
+    case 2: return batch_fn<2>();
+    case 4: return batch_fn<4>();
+    default: return batch_fn<6>();
+  }
+}
+
+hipError_t batch_blocks_per_cu(int variant, int *blocks) {
+  const void *fn = batch_kernel_ptr(variant);
+  const size_t lds = batch_lds_bytes(variant);
+  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, fn, kBlock, lds);
+}
+
+hipError_t launch_batch_reset(uint32_t *counter, hipStream_t stream) {
+  hipLaunchKernelGGL(batch_reset_kernel, dim3(1), dim3(64), 0, stream, counter);
+  return hipGetLastError();
+}
+
+template <int V>
+static hipError_t launch_batch_v(const BatchLaunch &b, int grid, hipStream_t stream) {
+  const size_t lds = Geom<V>::lds_bytes();
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(batch_kernel<V>),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(batch_kernel<V>, dim3((unsigned)grid), dim3(kBlock), lds, stream, b);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch(const BatchLaunch &b, int variant, int grid, hipStream_t stream) {
+  if (grid <= 0) return hipSuccess;
+  switch (variant) {
+    case 2: return launch_batch_v<2>(b, grid, stream);
+    case 4: return launch_batch_v<4>(b, grid, stream);
+    default: return launch_batch_v<6>(b, grid, stream);
   }
 }
 

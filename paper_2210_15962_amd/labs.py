@@ -45,6 +45,29 @@ class Plan(ctypes.Structure):
                 ("max_concurrent", I64)]
 
 
+class Instance(ctypes.Structure):
+    _fields_ = [("L", I32), ("lanes_per_walk", I32), ("n_walks", I64), ("walk_len", I64),
+                ("seed", U64), ("starts", VP), ("load_factor", ctypes.c_double),
+                ("out", WalkOut)]
+
+
+class ServeCfg(ctypes.Structure):
+    _fields_ = [("pool_bytes", U64), ("max_pending", I32), ("lanes_per_walk", I32),
+                ("chunk_steps", I64), ("load_factor", ctypes.c_double)]
+
+
+class ServeResult(ctypes.Structure):
+    _fields_ = [("best_seq", VP), ("best_E", VP), ("steps_done", VP), ("digest", VP),
+                ("t_submit_ns", I64), ("t_admit_ns", I64), ("t_done_ns", I64),
+                ("total_steps", I64)]
+
+
+class ServeCounters(ctypes.Structure):
+    _fields_ = [("submitted", I64), ("admitted", I64), ("completed", I64), ("pending", I64),
+                ("active", I64), ("launches", I64), ("walk_steps", I64), ("busy_ns", I64),
+                ("pool_bytes", U64), ("pool_used", U64), ("pool_peak", U64)]
+
+
 _lib = None
 
 
@@ -78,6 +101,36 @@ def lib():
         L.labs_walks.argtypes = [VP, I32, I64, I64, U64, ctypes.POINTER(WalkOut), VP, U64,
                                  ctypes.POINTER(Plan), VP]
         L.labs_walks.restype = I32
+        L.labs_batch_workspace_bytes.argtypes = [ctypes.POINTER(Instance), I32, ctypes.POINTER(U64)]
+        L.labs_batch_workspace_bytes.restype = I32
+        L.labs_walks_batch.argtypes = [ctypes.POINTER(Instance), I32, VP, U64, VP]
+        L.labs_walks_batch.restype = I32
+        L.labs_batch_graph_create.argtypes = [ctypes.POINTER(Instance), I32, VP, U64,
+                                              ctypes.POINTER(VP)]
+        L.labs_batch_graph_create.restype = I32
+        L.labs_batch_graph_launch.argtypes = [VP, VP]
+        L.labs_batch_graph_launch.restype = I32
+        L.labs_batch_graph_destroy.argtypes = [VP]
+        L.labs_batch_graph_destroy.restype = I32
+        L.labs_tune_set.argtypes = [I32, I32, ctypes.c_double]
+        L.labs_tune_set.restype = I32
+        L.labs_tune_get.argtypes = [I32, ctypes.POINTER(I32), ctypes.POINTER(ctypes.c_double)]
+        L.labs_tune_get.restype = I32
+        L.labs_autotune.argtypes = [I32, I64, I64, VP, U64, VP, ctypes.POINTER(I32),
+                                    ctypes.POINTER(ctypes.c_double)]
+        L.labs_autotune.restype = I32
+        L.labs_serve_create.argtypes = [ctypes.POINTER(ServeCfg), ctypes.POINTER(VP)]
+        L.labs_serve_create.restype = I32
+        L.labs_serve_destroy.argtypes = [VP]
+        L.labs_serve_destroy.restype = I32
+        L.labs_serve_submit.argtypes = [VP, I32, I64, I64, U64, VP, ctypes.POINTER(U64)]
+        L.labs_serve_submit.restype = I32
+        L.labs_serve_poll.argtypes = [VP, U64, ctypes.POINTER(ServeResult)]
+        L.labs_serve_poll.restype = I32
+        L.labs_serve_wait.argtypes = [VP, U64, I64, ctypes.POINTER(ServeResult)]
+        L.labs_serve_wait.restype = I32
+        L.labs_serve_stats.argtypes = [VP, ctypes.POINTER(ServeCounters)]
+        L.labs_serve_stats.restype = I32
         _lib = L
     return _lib
 
@@ -213,3 +266,186 @@ def walks(L: int, n_walks: int, walk_len: int, seed: int = 0, starts_t=None, n_t
                             ctypes.byref(out), _dptr(workspace), workspace.numel(),
                             ctypes.byref(plan) if plan else None, _stream_handle(stream)))
     return res
+
+
+# ----------------------------------------------------------- mixed-L batches
+def _alloc_outputs(L, n_walks, walk_len, n_trace, device="cuda"):
+    import torch
+    W = key_words(L)
+    res = {
+        "best_seq": torch.empty((n_walks, W), dtype=torch.int64, device=device),
+        "best_E": torch.empty(n_walks, dtype=torch.int32, device=device),
+        "steps_done": torch.empty(n_walks, dtype=torch.int64, device=device),
+        "digest": torch.empty(n_walks, dtype=torch.int64, device=device),
+    }
+    if n_trace:
+        res["trace_j"] = torch.zeros((n_trace, walk_len), dtype=torch.int16, device=device)
+        res["trace_E"] = torch.zeros((n_trace, walk_len), dtype=torch.int32, device=device)
+    return res
+
+
+def make_instances(specs, results):
+    """ctypes array of labs_instance from dicts (L, n_walks, walk_len, seed, starts_t,
+    lanes_per_walk, load_factor, n_trace) and their output tensors."""
+    arr = (Instance * max(len(specs), 1))()
+    for i, (sp, res) in enumerate(zip(specs, results)):
+        st = sp.get("starts_t")
+        out = WalkOut(_dptr(res["best_seq"]), _dptr(res["best_E"]), _dptr(res["steps_done"]),
+                      _dptr(res["digest"]), _dptr(res.get("trace_j")), _dptr(res.get("trace_E")),
+                      int(sp.get("n_trace", 0)))
+        arr[i] = Instance(int(sp["L"]), int(sp.get("lanes_per_walk", 0)), int(sp["n_walks"]),
+                          int(sp["walk_len"]), int(sp.get("seed", 0)) & 0xFFFFFFFFFFFFFFFF,
+                          _dptr(st), float(sp.get("load_factor", 0.0)), out)
+    return arr
+
+
+def batch_workspace_bytes(specs, results=None) -> int:
+    results = results or [_alloc_outputs(sp["L"], 0, 0, 0) for sp in specs]
+    arr = make_instances(specs, results)
+    b = U64(0)
+    _check(lib().labs_batch_workspace_bytes(arr, len(specs), ctypes.byref(b)))
+    return int(b.value)
+
+
+def walks_batch(specs, workspace=None, stream=None, device="cuda"):
+    """Run several instances (list of dicts, see make_instances) in one launch.
+    Returns one result dict per instance, like walks()."""
+    results = [_alloc_outputs(sp["L"], sp["n_walks"], sp["walk_len"], sp.get("n_trace", 0), device)
+               for sp in specs]
+    arr = make_instances(specs, results)
+    if workspace is None:
+        b = U64(0)
+        _check(lib().labs_batch_workspace_bytes(arr, len(specs), ctypes.byref(b)))
+        workspace = alloc_workspace(b.value, device=device)
+    _check(lib().labs_walks_batch(arr, len(specs), _dptr(workspace), workspace.numel(),
+                                  _stream_handle(stream)))
+    return results
+
+
+class BatchGraph:
+    """hipGraph of one mixed-L batch: create once, replay with launch()."""
+
+    def __init__(self, specs, workspace=None, device="cuda"):
+        self.specs = specs
+        self.results = [_alloc_outputs(sp["L"], sp["n_walks"], sp["walk_len"], sp.get("n_trace", 0),
+                                       device) for sp in specs]
+        self._arr = make_instances(specs, self.results)
+        if workspace is None:
+            b = U64(0)
+            _check(lib().labs_batch_workspace_bytes(self._arr, len(specs), ctypes.byref(b)))
+            workspace = alloc_workspace(b.value, device=device)
+        self.workspace = workspace
+        h = VP()
+        _check(lib().labs_batch_graph_create(self._arr, len(specs), _dptr(workspace),
+                                             workspace.numel(), ctypes.byref(h)))
+        self._h = h
+
+    def launch(self, stream=None):
+        _check(lib().labs_batch_graph_launch(self._h, _stream_handle(stream)))
+        return self.results
+
+    def close(self):
+        if self._h:
+            lib().labs_batch_graph_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def tune_set(L: int, lanes_per_walk: int, load_factor: float):
+    _check(lib().labs_tune_set(L, lanes_per_walk, load_factor))
+
+
+def tune_get(L: int):
+    g, lf = I32(0), ctypes.c_double(0)
+    rc = lib().labs_tune_get(L, ctypes.byref(g), ctypes.byref(lf))
+    if rc not in (LABS_OK, LABS_ENOTFOUND):
+        _check(rc)
+    return int(g.value), float(lf.value), rc == LABS_OK
+
+
+def autotune(L: int, n_walks: int = 4096, walk_len: int = 1024, stream=None, device="cuda"):
+    """Time lanes per walk / load factor for L on a short run; stores and returns the best."""
+    W = key_words(L)
+    need = workspace_bytes(L, n_walks, walk_len, make_plan(2, 0.5)) + \
+        ((n_walks * (8 * W + 12) + 255) // 256) * 256
+    ws = alloc_workspace(need, device=device)
+    g, lf = I32(0), ctypes.c_double(0)
+    _check(lib().labs_autotune(L, n_walks, walk_len, _dptr(ws), ws.numel(), _stream_handle(stream),
+                               ctypes.byref(g), ctypes.byref(lf)))
+    return int(g.value), float(lf.value)
+
+
+class Server:
+    """Continuous-batching walk server (labs_serve_* in include/labs.h).
+
+    submit() queues one request and returns its id; poll()/wait() return None
+    while it runs and a dict of host arrays (best_seq, best_E, steps_done,
+    digest) plus submit/admit/done times once it is done.
+    """
+
+    def __init__(self, pool_bytes: int = 0, max_pending: int = 0, lanes_per_walk: int = 0,
+                 chunk_steps: int = 0, load_factor: float = 0.0):
+        cfg = ServeCfg(pool_bytes, max_pending, lanes_per_walk, chunk_steps, load_factor)
+        h = VP()
+        _check(lib().labs_serve_create(ctypes.byref(cfg), ctypes.byref(h)))
+        self._h = h
+        self._shape = {}
+
+    def submit(self, L: int, n_walks: int, walk_len: int, seed: int = 0, starts=None) -> int:
+        st = None
+        if starts is not None:
+            st = np.ascontiguousarray(np.asarray(starts, dtype=np.uint64).reshape(n_walks, key_words(L)))
+        rid = U64(0)
+        _check(lib().labs_serve_submit(self._h, L, n_walks, walk_len, seed,
+                                       None if st is None else st.ctypes.data, ctypes.byref(rid)))
+        self._shape[rid.value] = (L, n_walks)
+        return int(rid.value)
+
+    def _result(self, rid, call):
+        L, n = self._shape.get(rid, (3, 0))      # unknown ids: the library reports them
+        W = key_words(L)
+        out = dict(best_seq=np.zeros((n, W), np.uint64), best_E=np.zeros(n, np.int32),
+                   steps_done=np.zeros(n, np.int64), digest=np.zeros(n, np.uint64))
+        res = ServeResult(out["best_seq"].ctypes.data, out["best_E"].ctypes.data,
+                          out["steps_done"].ctypes.data, out["digest"].ctypes.data, 0, 0, 0, 0)
+        rc = _check(call(ctypes.byref(res)))
+        if rc == LABS_PENDING:
+            return None
+        self._shape.pop(rid, None)
+        out.update(t_submit_ns=res.t_submit_ns, t_admit_ns=res.t_admit_ns, t_done_ns=res.t_done_ns,
+                   total_steps=res.total_steps)
+        return out
+
+    def poll(self, rid: int):
+        return self._result(rid, lambda r: lib().labs_serve_poll(self._h, rid, r))
+
+    def wait(self, rid: int, timeout_s: Optional[float] = None):
+        t = -1 if timeout_s is None else int(timeout_s * 1e9)
+        return self._result(rid, lambda r: lib().labs_serve_wait(self._h, rid, t, r))
+
+    def stats(self) -> dict:
+        c = ServeCounters()
+        _check(lib().labs_serve_stats(self._h, ctypes.byref(c)))
+        return {k: getattr(c, k) for k, _ in ServeCounters._fields_}
+
+    def close(self):
+        if self._h:
+            lib().labs_serve_destroy(self._h)
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

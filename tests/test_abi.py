@@ -118,3 +118,47 @@ def test_energy_argument_errors_before_any_launch():
     assert lib.labs_energy(None, 10, 1, None, None) == labs.LABS_EINVAL
     assert lib.labs_energy(None, 10, 0, None, None) == labs.LABS_OK
     assert lib.labs_starts(28, 1, 0, ctypes.c_void_p(1), None) == labs.LABS_EINVAL
+
+
+def test_tune_table_roundtrip():
+    lib = labs.lib()
+    assert lib.labs_tune_set(28, 4, 0.5) == labs.LABS_EINVAL
+    assert lib.labs_tune_set(29, 3, 0.5) == labs.LABS_EINVAL
+    assert lib.labs_tune_set(29, 4, 0.95) == labs.LABS_EINVAL
+    g, lf, found = labs.tune_get(31)
+    assert (g, lf, found) == (4, 0.5, False)          # built-in default
+    labs.tune_set(31, 8, 0.67)
+    assert labs.tune_get(31) == (8, 0.67, True)
+    labs.tune_set(31, 4, 0.5)
+
+
+def test_batch_validation_before_any_launch():
+    lib = labs.lib()
+    empty = {"best_seq": None, "best_E": None, "steps_done": None, "digest": None}
+    arr = labs.make_instances([dict(L=28, n_walks=4, walk_len=10)], [empty])
+    ws = ctypes.c_void_p(1)
+    assert lib.labs_walks_batch(arr, 1, ws, 1 << 30, None) == labs.LABS_EINVAL
+    b = labs.U64(0)
+    assert lib.labs_batch_workspace_bytes(arr, 1, ctypes.byref(b)) == labs.LABS_EINVAL
+    arr = labs.make_instances([dict(L=27, n_walks=4, walk_len=10, lanes_per_walk=1)], [empty])
+    assert lib.labs_walks_batch(arr, 1, ws, 1 << 30, None) == labs.LABS_EINVAL   # batches: 2/4/8
+    arr = labs.make_instances([dict(L=27, n_walks=4, walk_len=10)], [empty])
+    assert lib.labs_walks_batch(arr, 1, ws, 1 << 30, None) == labs.LABS_EINVAL   # no outputs
+    assert lib.labs_walks_batch(arr, -1, ws, 1 << 30, None) == labs.LABS_EINVAL
+    assert lib.labs_walks_batch(arr, 0, ws, 0, None) == labs.LABS_OK            # nothing to run
+
+
+def test_serve_validation_before_any_device_call():
+    lib = labs.lib()
+    h = ctypes.c_void_p()
+    assert lib.labs_serve_create(None, None) == labs.LABS_EINVAL
+    for cfg in [labs.ServeCfg(0, 0, 3, 0, 0.0), labs.ServeCfg(0, -1, 0, 0, 0.0),
+                labs.ServeCfg(0, 0, 0, -5, 0.0), labs.ServeCfg(0, 0, 0, 0, 0.95)]:
+        assert lib.labs_serve_create(ctypes.byref(cfg), ctypes.byref(h)) == labs.LABS_EINVAL
+        assert not h.value
+    rid = labs.U64(0)
+    assert lib.labs_serve_submit(None, 27, 1, 1, 0, None, ctypes.byref(rid)) == labs.LABS_EINVAL
+    assert lib.labs_serve_poll(None, 1, None) == labs.LABS_EINVAL
+    assert lib.labs_serve_wait(None, 1, 0, None) == labs.LABS_EINVAL
+    assert lib.labs_serve_stats(None, None) == labs.LABS_EINVAL
+    assert lib.labs_serve_destroy(None) == labs.LABS_OK
