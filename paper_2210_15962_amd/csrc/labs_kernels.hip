@@ -71,6 +71,14 @@ __device__ __forceinline__ uint32_t umed3(uint32_t a, uint32_t b, uint32_t c) {
   return r;
 }
 
+// (a << S) + b as one v_lshl_add_u32 (kept as a chain, not reassociated).
+template <int S>
+__device__ __forceinline__ uint32_t lshl_add(uint32_t a, uint32_t b) {
+  uint32_t r;
+  asm("v_lshl_add_u32 %0, %1, %2, %3" : "=v"(r) : "v"(a), "I"(S), "v"(b));
+  return r;
+}
+
 __device__ __forceinline__ uint32_t funnel(uint32_t hi, uint32_t lo, uint32_t sh) {
   return __builtin_amdgcn_alignbit(hi, lo, sh);
 }
@@ -130,6 +138,10 @@ __host__ __device__ constexpr int plane_off(int nw, int w) {
   return s;
 }
 
+// Run table: iterations of the candidate loop grouped into runs of constant
+// lag-word counts; slot kRunSlots-1 holds the number of runs.
+constexpr int kRunSlots = 16;
+
 template <int NW>
 struct Geom {
   static constexpr int NWB = (NW + 1) / 2;           // backward lag words
@@ -138,9 +150,14 @@ struct Geom {
   static constexpr int DESC = ((9 + NW + 2 * NWB) + 3) & ~3;  // dwords per row
   static constexpr int NPW = plane_off(NW, NW);      // plane words in total
   static constexpr int BMAX = planes_of(NW, 0);
-  static constexpr size_t lds_bytes() {
-    return (size_t)DMAX * DESC * 4 + (size_t)4 * NWA * kBlock * 4;
-  }
+  // Descriptor rows: D real rows plus dead rows up to a multiple of the
+  // lanes per walk (<= 8), so every lane of the candidate loop reads a row.
+  static constexpr int DROWS = DMAX + 8;
+  // The lane columns start on a 256-byte boundary (two-address LDS reads
+  // with 256-byte strides need no extra base adjustment).
+  static constexpr size_t cols_off() { return ((size_t)DROWS * DESC * 4 + 255) & ~(size_t)255; }
+  static constexpr size_t runs_off() { return cols_off() + (size_t)4 * NWA * kBlock * 4; }
+  static constexpr size_t lds_bytes() { return runs_off() + kRunSlots * 4; }
 };
 
 // Descriptor row of candidate j (dword offsets).
@@ -151,8 +168,8 @@ enum : int {
   DS_BSH = 3,
   DS_SOFF = 4,   // byte offset of the word holding s_j
   DS_SPOS = 5,   // bit position of s_j in that word
-  DS_KC = 6,     // 2N + 4|MF & MB| + kBias
-  DS_N = 7,      // |MF| + |MB|
+  DS_KC = 6,     // (((2N - 4|MF & MB| + kBias) << 8) | (j - 1)) + 1; dead rows: 0
+  DS_N = 7,      // (N - 2 sum_w 2^(B_w - 1) (|MF_w| + |MB_w|)) << 8, two's complement
   DS_JM1 = 8,    // j - 1
   DS_MASKS = 9   // MF[NW], MB[NWB], MFB[NWB]
 };
@@ -194,13 +211,14 @@ __device__ __forceinline__ void build_descriptors(uint32_t *desc, int L) {
     const int nF = (j < D) ? n_c - 1 - r : 0;    // forward lags inside [1, L]
     const int nB = r;                            // backward lags inside [1, L]
     const int hole = (j < D) ? D - 1 - j : -1;   // lag index of k0 = L+1-2j
-    int cntF = 0, cntB = 0, cntFB = 0;
+    int cntF = 0, cntB = 0, cntFB = 0, signw = 0;
 #pragma unroll
     for (int w = 0; w < NW; ++w) {
       uint32_t mf = prefix_mask(nF, w);
       if (hole >= 32 * w && hole < 32 * w + 32) mf &= ~(1u << (hole - 32 * w));
       row[DS_MASKS + w] = mf;
       cntF += __builtin_popcount(mf);
+      int nw_bits = __builtin_popcount(mf);
       if (w < Gm::NWB) {
         const uint32_t mb = prefix_mask(nB, w);
         const uint32_t mfb = mb & mf;
@@ -208,15 +226,20 @@ __device__ __forceinline__ void build_descriptors(uint32_t *desc, int L) {
         row[DS_MASKS + NW + Gm::NWB + w] = mfb;
         cntB += __builtin_popcount(mb);
         cntFB += __builtin_popcount(mfb);
+        nw_bits += __builtin_popcount(mb);
       }
+      // the sign plane of word w is counted complemented (see eval_key)
+      signw += nw_bits << (planes_of(NW, w) - 1);
     }
     const int N = cntF + cntB;
-    row[DS_KC] = (uint32_t)(2 * N + 4 * cntFB + kBias);
-    row[DS_N] = (uint32_t)N;
+    row[DS_KC] = (((uint32_t)(2 * N - 4 * cntFB + kBias) << 8) | (uint32_t)(j - 1)) + 1u;
+    row[DS_N] = (uint32_t)(N - 2 * signw) << 8;
     row[DS_JM1] = (uint32_t)(j - 1);
 #pragma unroll
     for (int i = DS_MASKS + NW + 2 * Gm::NWB; i < Gm::DESC; ++i) row[i] = 0;
   }
+  // Dead rows D+1 .. D+8: all zero, which gives the key ~0 (never chosen).
+  for (int t = (int)threadIdx.x; t < 8 * Gm::DESC; t += blockDim.x) desc[D * Gm::DESC + t] = 0u;
 }
 
 // Forward / backward neighbour bit vectors of candidate j, its masks and s_j.
@@ -228,7 +251,6 @@ struct CandVec {
   uint32_t mb[Geom<NW>::NWB];
   uint32_t mfb[Geom<NW>::NWB];
   uint32_t sbit;
-  int32_t kc, N;
   uint32_t jm1;
 };
 
@@ -241,8 +263,6 @@ __device__ __forceinline__ void load_candidate(const uint32_t *desc_row, const u
   using Gm = Geom<NW>;
   const uint4 d0 = *reinterpret_cast<const uint4 *>(desc_row);
   const uint4 d1 = *reinterpret_cast<const uint4 *>(desc_row + 4);
-  cv.kc = (int32_t)d1.z;
-  cv.N = (int32_t)d1.w;
   cv.jm1 = desc_row[DS_JM1];
   const uint32_t *fsrc = reinterpret_cast<const uint32_t *>(lds + colbase + d0.x);
   const uint32_t *bsrc = reinterpret_cast<const uint32_t *>(lds + colbase + d0.z);
@@ -278,72 +298,137 @@ __device__ __forceinline__ void load_candidate(const uint32_t *desc_row, const u
   cv.sbit = (sw >> d1.y) & 1u;
 }
 
-// Candidate key: ((dE/8 + kBias) << 8) | (j-1).  Unsigned order = (dE, j) order.
-// Words at or beyond FW (forward) / BW (backward) are skipped (wave-uniform).
-template <int NW>
-__device__ __forceinline__ uint32_t candidate_key(const CandVec<NW> &cv, const uint32_t *P,
-                                                  int FW, int BW) {
+// Candidate key of j: ((dE/8 + kBias) << 8) | (j-1), so unsigned order is
+// (dE, j) order.  FW forward and BW backward lag words are evaluated; the
+// caller guarantees that candidate j has no lag in any later word (its masks
+// there are zero), so those words contribute nothing.
+//
+// Per plane b of word w the count is popcount((c_b XOR f) AND M); for the
+// sign plane (b = B_w - 1) the complement popcount(NOT(c_b XOR f) AND M) =
+// |M| - popcount(...) is taken instead, so every plane enters the Horner sum
+// with a positive weight and the |M| 2^(B_w - 1) excess is a per-candidate
+// constant folded into the descriptor (DS_N).
+template <int NW, int FW, int BW>
+__device__ __forceinline__ uint32_t eval_key(const uint32_t *row, const uint8_t *lds,
+                                             uint32_t colbase, const uint32_t *P) {
   using Gm = Geom<NW>;
+  static_assert(FW >= 1 && FW <= NW && BW <= Gm::NWB && BW <= FW, "lag-word counts");
   constexpr int BM = Gm::BMAX;
-  uint32_t cnt[BM - 1];
+  const uint4 d0 = *reinterpret_cast<const uint4 *>(row);
+  const uint4 d1 = *reinterpret_cast<const uint4 *>(row + 4);
+  const uint32_t *fsrc = reinterpret_cast<const uint32_t *>(lds + colbase + d0.x);
+  const uint32_t *bsrc = reinterpret_cast<const uint32_t *>(lds + colbase + d0.z);
+  const uint32_t sw = *reinterpret_cast<const uint32_t *>(lds + colbase + d1.x);
+  uint32_t fv[FW];
+  uint32_t bv[BW > 0 ? BW : 1];
+  {
+    uint32_t lo = fsrc[0];
 #pragma unroll
-  for (int b = 0; b < BM - 1; ++b) cnt[b] = 0;
-  int32_t X = 0;
-  static_for<0, NW>([&](auto wc) {
+    for (int w = 0; w < FW; ++w) {
+      const uint32_t hi = fsrc[(w + 1) * kBlock];
+      fv[w] = funnel(hi, lo, d0.y);
+      lo = hi;
+    }
+  }
+  if constexpr (BW > 0) {
+    uint32_t lo = bsrc[0];
+#pragma unroll
+    for (int w = 0; w < BW; ++w) {
+      const uint32_t hi = bsrc[(w + 1) * kBlock];
+      bv[w] = funnel(hi, lo, d0.w);
+      lo = hi;
+    }
+  }
+  uint32_t cnt[BM];
+#pragma unroll
+  for (int b = 0; b < BM; ++b) cnt[b] = 0u;
+  uint32_t q = 0u;
+  static_for<0, FW>([&](auto wc) {
     constexpr int w = decltype(wc)::value;
     constexpr int Bw = planes_of(NW, w), off = plane_off(NW, w);
-    if (w < FW) {
-      uint32_t s = 0;
+    const uint32_t mf = row[DS_MASKS + w];
 #pragma unroll
-      for (int b = 0; b < Bw - 1; ++b) cnt[b] = popc_add((P[off + b] ^ cv.fw[w]) & cv.mf[w], cnt[b]);
-      s = popc_add((P[off + Bw - 1] ^ cv.fw[w]) & cv.mf[w], s);
-      if constexpr (w < Gm::NWB) {
-        if (w < BW) {
+    for (int b = 0; b < Bw - 1; ++b) cnt[b] = popc_add((P[off + b] ^ fv[w]) & mf, cnt[b]);
+    cnt[Bw - 1] = popc_add(~(P[off + Bw - 1] ^ fv[w]) & mf, cnt[Bw - 1]);
+    if constexpr (w < BW) {
+      const uint32_t mb = row[DS_MASKS + NW + w];
 #pragma unroll
-          for (int b = 0; b < Bw - 1; ++b) cnt[b] = popc_add((P[off + b] ^ cv.bw[w]) & cv.mb[w], cnt[b]);
-          s = popc_add((P[off + Bw - 1] ^ cv.bw[w]) & cv.mb[w], s);
-        }
-      }
-      X -= (int32_t)(s << (Bw - 1));   // sign plane of this word
+      for (int b = 0; b < Bw - 1; ++b) cnt[b] = popc_add((P[off + b] ^ bv[w]) & mb, cnt[b]);
+      cnt[Bw - 1] = popc_add(~(P[off + Bw - 1] ^ bv[w]) & mb, cnt[Bw - 1]);
+      q = popc_add(~(fv[w] ^ bv[w]) & row[DS_MASKS + NW + Gm::NWB + w], q);   // |MFB| - q
     }
   });
-  // X += sum_b 2^b cnt_b  (Horner), giving sum over masked lags of (c_t XOR -f_t).
-  int32_t Hn = (int32_t)cnt[BM - 2];
+  uint32_t H = cnt[BM - 1];
 #pragma unroll
-  for (int b = BM - 3; b >= 0; --b) Hn = 2 * Hn + (int32_t)cnt[b];
-  X += Hn;
-  uint32_t q = 0;
-#pragma unroll
-  for (int w = 0; w < Gm::NWB; ++w)
-    if (w < BW) q = popc_add((cv.fw[w] ^ cv.bw[w]) & cv.mfb[w], q);
-  const int32_t Y = 2 * X + cv.N;
-  const int32_t Z = cv.kc - 8 * (int32_t)q;
-  const int32_t val = cv.sbit ? Z + Y : Z - Y;
-  return ((uint32_t)val << 8) | cv.jm1;
+  for (int b = BM - 2; b >= 0; --b) H = lshl_add<1>(H, cnt[b]);
+  const uint32_t t = lshl_add<9>(H, d1.w);      // (2 X + N) << 8
+  const uint32_t kq = lshl_add<11>(q, d1.z);    // (((kc - 8 q) << 8) | (j - 1)) + 1
+  // s_j = -1 (bit set, sg = ~0): kq - 1 + t; else kq + ~t = kq - 1 - t.
+  const uint32_t sg = (uint32_t)__builtin_amdgcn_sbfe((int)sw, (int)d1.y, 1);
+  return kq + sg + ~(t ^ sg);
 }
 
 // Lag words some candidate of iteration i (j = G*i + 1 .. G*i + G) needs:
 // forward words cover the largest forward range (smallest j of either class),
-// backward words the largest backward range (largest j).
-template <int NW>
-__device__ __forceinline__ void iteration_words(int i, int D, int G, int &FW, int &BW) {
-  using Gm = Geom<NW>;
+// backward words the largest backward range (largest j).  Returns FW*8 + BW
+// with 1 <= FW <= nw, BW <= FW.
+__host__ __device__ constexpr int words_of(int i, int D, int G, int nw) {
   const int m = D - 1;
+  const int nwb = (nw + 1) / 2;
   const int jlo = G * i + 1;
-  const int jhi = min(G * i + G, D);
-  auto nF = [&](int j) -> int {
-    if (j >= D) return 0;
+  const int jhi = (G * i + G < D) ? G * i + G : D;
+  int f = 0;
+  for (int j = jlo; j <= jlo + 1 && j < D; ++j) {
     const int nc = (j & 1) ? D : m;
-    return nc - 1 - ((j - 1) >> 1);
-  };
-  int f = nF(jlo);
-  if (jlo + 1 <= D) f = max(f, nF(jlo + 1));
+    const int nf = nc - 1 - ((j - 1) >> 1);
+    f = nf > f ? nf : f;
+  }
   const int b = (jhi - 1) >> 1;
-  BW = min(Gm::NWB, (b + 31) >> 5);
-  // The per-word loop of candidate_key visits w < FW and nests the backward
-  // planes inside it, so FW must cover BW (the centre j = D alone has no
-  // forward lags but still has backward ones).
-  FW = max(min(NW, (f + 31) >> 5), BW);
+  int bw = (b + 31) >> 5;
+  bw = bw < nwb ? bw : nwb;
+  int fw = (f + 31) >> 5;
+  fw = fw < nw ? fw : nw;
+  fw = fw > bw ? fw : bw;
+  fw = fw > 1 ? fw : 1;
+  return fw * 8 + bw;
+}
+
+// Set of (FW, BW) codes the candidate loop of a kernel compiled for lag-word
+// class nw can meet: lengths of exactly that class (walk kernel) or of every
+// class up to it (batch kernel), for G lanes per walk.
+__host__ __device__ constexpr uint64_t words_mask(int nw, int G, bool exact_class) {
+  uint64_t mask = 0;
+  for (int L = 3; L <= lmax_of(nw); L += 2) {
+    const int m = (L - 1) / 2, D = (L + 1) / 2;
+    const int cls = (m + 31) / 32;
+    if (exact_class ? cls != nw : cls > nw) continue;
+    for (int i = 0; i < (D + G - 1) / G; ++i) mask |= 1ull << words_of(i, D, G, nw);
+  }
+  return mask;
+}
+
+template <int NW, int G>
+struct WordsMask {
+  static constexpr uint64_t value =
+      G > 0 ? words_mask(NW, G, true)
+            : (words_mask(NW, 2, false) | words_mask(NW, 4, false) | words_mask(NW, 8, false));
+};
+
+// Calls f(FW, BW) as compile-time constants for a wave-uniform code; a code
+// outside MASK takes the all-words form, which is valid for every candidate.
+// Each instantiation of f has exactly one call site.
+template <int NW, uint64_t MASK, class F>
+__device__ __forceinline__ void with_words(int code, F &&f) {
+  constexpr int kFull = NW * 8 + Geom<NW>::NWB;
+  constexpr uint64_t kAll = MASK | (1ull << kFull);
+  const int eff = ((kAll >> (code & 63)) & 1ull) != 0 ? code : kFull;
+  static_for<8, 64>([&](auto cc) {
+    constexpr int c = decltype(cc)::value;
+    constexpr int fw = c >> 3, bw = c & 7;
+    if constexpr (((kAll >> c) & 1ull) != 0 && fw <= NW && bw <= Geom<NW>::NWB && bw <= fw) {
+      if (eff == c) f(std::integral_constant<int, fw>{}, std::integral_constant<int, bw>{});
+    }
+  });
 }
 
 // c_t += 2u_t on the bit planes for the move j (u from the pre-move vectors):
@@ -497,11 +582,31 @@ __device__ __forceinline__ void run_block(const BlockTask &a, uint8_t *lds) {
   using Gm = Geom<NW>;
   const int Gl = (G > 0) ? G : a.lanes;        // lanes per walk (wave-uniform)
   uint32_t *desc = reinterpret_cast<uint32_t *>(lds);
-  uint8_t *cols = lds + (size_t)Gm::DMAX * Gm::DESC * 4;
+  uint8_t *cols = lds + Gm::cols_off();
 
   const int L = a.L, D = (L + 1) / 2, m = (L - 1) / 2;
   const int KW = (D + 63) / 64;
   build_descriptors<NW>(desc, L);
+  uint32_t *runs = reinterpret_cast<uint32_t *>(lds + Gm::runs_off());
+  const int nmax = (D + Gl - 1) / Gl;           // candidate-loop iterations
+  if (threadIdx.x == 0) {
+    // Runs of iterations with equal lag-word counts: (first i << 8) | code,
+    // then a sentinel (nmax << 8).  Past kRunSlots - 2 runs the last run takes
+    // the all-words form, which serves any candidate.
+    int n = 0, prev = -1;
+    for (int i = 0; i < nmax; ++i) {
+      const int code = words_of(i, D, Gl, NW);
+      if (code == prev) continue;
+      if (n == kRunSlots - 2) {
+        runs[n - 1] = (runs[n - 1] & ~0xFFu) | (uint32_t)(NW * 8 + Gm::NWB);
+        break;
+      }
+      runs[n++] = ((uint32_t)i << 8) | (uint32_t)code;
+      prev = code;
+    }
+    runs[n] = (uint32_t)nmax << 8;
+    runs[kRunSlots - 1] = (uint32_t)n;
+  }
   if (!a.resume) {
     // Clear the visited tables of this block's walks (contiguous, coalesced).
     uint4 *p = reinterpret_cast<uint4 *>(a.tables);
@@ -623,6 +728,8 @@ __device__ __forceinline__ void run_block(const BlockTask &a, uint8_t *lds) {
 
   // Local candidates of lane r: j = r + 1 + Gl*i.
   const int ncand = (D - r + Gl - 1) / Gl;       // may be 0 for r >= D
+  const int nruns = (int)__builtin_amdgcn_readfirstlane(runs[kRunSlots - 1]);
+  constexpr uint64_t kMask = WordsMask<NW, G>::value;
   const bool tracing = active && walk < a.n_trace;
 
   // Every walk still moving has made exactly step_begin moves (trapped walks
@@ -653,20 +760,23 @@ __device__ __forceinline__ void run_block(const BlockTask &a, uint8_t *lds) {
     bool done = !active;
     uint32_t win = kKeyMax;
 
-    const int nmax = (D + Gl - 1) / Gl;
     // (0) main scan: every local candidate goes into the top-K.
 #pragma unroll
     for (int i = 0; i < K; ++i) tk[i] = kKeyMax;
 #pragma unroll 1
-    for (int i = 0; i < nmax; ++i) {
-      int FW, BW;
-      iteration_words<NW>(i, D, Gl, FW, BW);
-      const bool live = i < ncand;
-      const int j = live ? (r + 1 + Gl * i) : 1;
-      CandVec<NW> cv;
-      load_candidate<NW>(desc + (j - 1) * Gm::DESC, cols, colbase, cv, FW, BW);
-      const uint32_t key = candidate_key<NW>(cv, Pl, FW, BW);
-      if (live) topk_insert<K>(tk, key);
+    for (int sr = 0; sr < nruns; ++sr) {
+      const uint32_t e0 = __builtin_amdgcn_readfirstlane(runs[sr]);
+      const int ib = (int)(e0 >> 8);
+      const int ie = (int)(__builtin_amdgcn_readfirstlane(runs[sr + 1]) >> 8);
+      with_words<NW, kMask>((int)(e0 & 0xFFu), [&](auto Fc, auto Bc) __attribute__((always_inline)) {
+        constexpr int F = decltype(Fc)::value, B = decltype(Bc)::value;
+#pragma unroll 1
+        for (int i = ib; i < ie; ++i) {
+          // j > D reads a dead row whose key ~0 leaves the top-K unchanged
+          const int j = r + 1 + Gl * i;
+          topk_insert<K>(tk, eval_key<NW, F, B>(desc + (j - 1) * Gm::DESC, cols, colbase, Pl));
+        }
+      });
     }
     // The predecessor is visited: drop it from its owner's top-K.
     if (prev_jm1 != 0xFFFFFFFFu && (int)(prev_jm1 % Gl) == r) {
@@ -691,20 +801,31 @@ __device__ __forceinline__ void run_block(const BlockTask &a, uint8_t *lds) {
 #pragma unroll
           for (int i = 0; i < K; ++i) tk[i] = kKeyMax;
         }
-        uint64_t xw = 0ull;
+        const bool scanning = !done && need_scan;
 #pragma unroll 1
-        for (int i = 0; i < nmax; ++i) {
-          if ((i & 63) == 0) xw = (i < 64) ? ex0 : (i < 128) ? ex1 : ex2;
-          int FW, BW;
-          iteration_words<NW>(i, D, Gl, FW, BW);
-          const bool live = !done && need_scan && i < ncand;
-          const int j = live ? (r + 1 + Gl * i) : 1;
-          CandVec<NW> cv;
-          load_candidate<NW>(desc + (j - 1) * Gm::DESC, cols, colbase, cv, FW, BW);
-          uint32_t key = candidate_key<NW>(cv, Pl, FW, BW);
-          key |= 0u - (uint32_t)(xw & 1ull);
-          xw >>= 1;
-          if (live) topk_insert<K>(tk, key);
+        for (int sr = 0; sr < nruns; ++sr) {
+          const uint32_t e0 = __builtin_amdgcn_readfirstlane(runs[sr]);
+          const int ib = (int)(e0 >> 8);
+          const int ie = (int)(__builtin_amdgcn_readfirstlane(runs[sr + 1]) >> 8);
+          with_words<NW, kMask>((int)(e0 & 0xFFu), [&](auto Fc, auto Bc) __attribute__((always_inline)) {
+            constexpr int F = decltype(Fc)::value, B = decltype(Bc)::value;
+            // select with masks: a select chain becomes a stack lookup table
+            auto ex_word = [&](int qw) {
+              return (ex0 & (0ull - (uint64_t)(qw == 0))) | (ex1 & (0ull - (uint64_t)(qw == 1))) |
+                     (ex2 & (0ull - (uint64_t)(qw == 2)));
+            };
+            uint64_t xw = ex_word(ib >> 6) >> (ib & 63);
+#pragma unroll 1
+            for (int i = ib; i < ie; ++i) {
+              if ((i & 63) == 0) xw = ex_word(i >> 6);
+              const bool live = scanning && i < ncand;
+              const int j = r + 1 + Gl * i;             // j > D: dead row
+              uint32_t key = eval_key<NW, F, B>(desc + (j - 1) * Gm::DESC, cols, colbase, Pl);
+              key |= 0u - (uint32_t)(xw & 1ull);
+              xw >>= 1;
+              if (live) topk_insert<K>(tk, key);
+            }
+          });
         }
         if (!done && need_scan) {
           need_scan = false;
