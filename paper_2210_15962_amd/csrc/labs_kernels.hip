@@ -157,7 +157,8 @@ struct Geom {
   // with 256-byte strides need no extra base adjustment).
   static constexpr size_t cols_off() { return ((size_t)DROWS * DESC * 4 + 255) & ~(size_t)255; }
   static constexpr size_t runs_off() { return cols_off() + (size_t)4 * NWA * kBlock * 4; }
-  static constexpr size_t lds_bytes() { return runs_off() + kRunSlots * 4; }
+  static constexpr size_t zob_off() { return runs_off() + kRunSlots * 4; }
+  static constexpr size_t lds_bytes() { return zob_off() + (size_t)DMAX * 4; }
 };
 
 // Descriptor row of candidate j (dword offsets).
@@ -456,9 +457,9 @@ __device__ __forceinline__ void apply_move_planes(const CandVec<NW> &cv, uint32_
     for (int b = 1; b < Bw; ++b) {
       const uint32_t x = (b == 1) ? u0 : (b == 2) ? u1 : u2;
       const uint32_t p = P[off + b];
-      const uint32_t t = p ^ x;
-      P[off + b] = t ^ carry;
-      carry = (t & carry) | (p & x);
+      // truth tables over (p, x, carry) = (0xF0, 0xCC, 0xAA): 0x96 = XOR3, 0xE8 = majority
+      P[off + b] = __builtin_amdgcn_bitop3_b32(p, x, carry, 0x96);
+      carry = __builtin_amdgcn_bitop3_b32(p, x, carry, 0xE8);
     }
   });
 }
@@ -468,42 +469,48 @@ __device__ __forceinline__ void apply_move_planes(const CandVec<NW> &cv, uint32_
 // ---------------------------------------------------------------------------
 struct Key3 { uint64_t w0, w1, w2; };
 
-__device__ __forceinline__ uint32_t bucket_of(const Key3 &k, uint32_t n_buckets) {
-  uint64_t h = k.w0 * 0x9E3779B97F4A7C15ull ^ k.w1 * 0xC2B2AE3D27D4EB4Full ^
-               k.w2 * 0x165667B19E3779F9ull;
-  h = mix64(h);
-  return (uint32_t)(((h >> 32) * (uint64_t)n_buckets) >> 32);
+// Bucket of a key: an XOR-linear (Zobrist) hash -- the XOR of one random
+// 32-bit word per set free bit -- mapped onto [0, n_buckets) by a
+// multiply-high.  A walk keeps the hash of its pivot, so the hash of any
+// neighbour is one XOR away.  The table stores full keys, so the hash only
+// decides where a key is looked for, never whether it is found.
+__device__ __forceinline__ uint32_t zobrist_word(int jm1) {
+  return (uint32_t)(mix64(0xA0761D6478BD642Full + (uint64_t)jm1) >> 32);
+}
+__device__ __forceinline__ uint32_t bucket_of_hash(uint32_t h, uint32_t n_buckets) {
+  return __umulhi(h, n_buckets);
 }
 
 // Scan one bucket.  Returns 2 = key present, 1 = absent (slot = first free
-// entry), 0 = bucket full without the key.
+// entry), 0 = bucket full without the key.  Entries fill in order and are
+// never deleted, so a present key lies before the first free entry.  No
+// early exits: the four (or two) entries are tested with selects.
 __device__ __forceinline__ int scan_bucket(const uint8_t *bucket, const Key3 &k, bool e32,
                                            uint32_t &slot) {
   const uint4 *q = reinterpret_cast<const uint4 *>(bucket);
-  uint4 v0 = q[0], v1 = q[1], v2 = q[2], v3 = q[3];
+  const uint4 v0 = q[0], v1 = q[1], v2 = q[2], v3 = q[3];
   const uint32_t k0l = (uint32_t)k.w0, k0h = (uint32_t)(k.w0 >> 32);
   const uint32_t k1l = (uint32_t)k.w1, k1h = (uint32_t)(k.w1 >> 32);
+  bool found;
+  uint32_t free_slot;
   if (!e32) {
-    uint4 e[4] = {v0, v1, v2, v3};
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const bool occ = (e[i].w >> 31) != 0;
-      if (!occ) { slot = (uint32_t)i * 16u; return 1; }
-      if (e[i].x == k0l && e[i].y == k0h && e[i].z == k1l && (e[i].w & 0x7FFFFFFFu) == k1h) return 2;
-    }
-    return 0;
+    auto eq = [&](const uint4 &e) {
+      return e.x == k0l && e.y == k0h && e.z == k1l && e.w == (k1h | 0x80000000u);
+    };
+    found = eq(v0) || eq(v1) || eq(v2) || eq(v3);
+    free_slot = (v0.w >> 31) == 0u ? 0u : (v1.w >> 31) == 0u ? 16u :
+                (v2.w >> 31) == 0u ? 32u : (v3.w >> 31) == 0u ? 48u : 64u;
   } else {
     const uint32_t k2l = (uint32_t)k.w2, k2h = (uint32_t)(k.w2 >> 32);
-    uint4 lo[2] = {v0, v2}, hi[2] = {v1, v3};
-#pragma unroll
-    for (int i = 0; i < 2; ++i) {
-      const bool occ = hi[i].z != 0;
-      if (!occ) { slot = (uint32_t)i * 32u; return 1; }
-      if (lo[i].x == k0l && lo[i].y == k0h && lo[i].z == k1l && lo[i].w == k1h &&
-          hi[i].x == k2l && hi[i].y == k2h) return 2;
-    }
-    return 0;
+    auto eq = [&](const uint4 &lo, const uint4 &hi) {
+      return lo.x == k0l && lo.y == k0h && lo.z == k1l && lo.w == k1h && hi.x == k2l &&
+             hi.y == k2h && hi.z != 0u;
+    };
+    found = eq(v0, v1) || eq(v2, v3);
+    free_slot = v1.z == 0u ? 0u : v3.z == 0u ? 32u : 64u;
   }
+  slot = free_slot;
+  return found ? 2 : (free_slot < 64u ? 1 : 0);
 }
 
 __device__ __forceinline__ void store_entry(uint8_t *p, const Key3 &k, bool e32) {
@@ -607,6 +614,8 @@ __device__ __forceinline__ void run_block(const BlockTask &a, uint8_t *lds) {
     runs[n] = (uint32_t)nmax << 8;
     runs[kRunSlots - 1] = (uint32_t)n;
   }
+  uint32_t *zob = reinterpret_cast<uint32_t *>(lds + Gm::zob_off());
+  for (int j = (int)threadIdx.x; j < D; j += blockDim.x) zob[j] = zobrist_word(j);
   if (!a.resume) {
     // Clear the visited tables of this block's walks (contiguous, coalesced).
     uint4 *p = reinterpret_cast<uint4 *>(a.tables);
@@ -722,9 +731,14 @@ __device__ __forceinline__ void run_block(const BlockTask &a, uint8_t *lds) {
     if (trapped) active = false;
   }
 
+  // Hash of the pivot (XOR of the words of its set bits).
+  uint32_t hP = 0u;
+#pragma unroll 1
+  for (int jb = 0; jb < D; ++jb) hP ^= key_bit(P, jb) ? zob[jb] : 0u;
+
   // Insert P_1 (the table is empty: first entry of its home bucket).
   if (active && !a.resume && r == 0)
-    store_entry(table + (uint64_t)bucket_of(P, a.n_buckets) * kBucketBytes, P, e32);
+    store_entry(table + (uint64_t)bucket_of_hash(hP, a.n_buckets) * kBucketBytes, P, e32);
 
   // Local candidates of lane r: j = r + 1 + Gl*i.
   const int ncand = (D - r + Gl - 1) / Gl;       // may be 0 for r >= D
@@ -842,7 +856,7 @@ __device__ __forceinline__ void run_block(const BlockTask &a, uint8_t *lds) {
         const uint32_t hk = head;
         if (!pstarted) {
           pkey = flip_key(P, hk & 0xFFu);
-          pbucket = bucket_of(pkey, a.n_buckets);
+          pbucket = bucket_of_hash(hP ^ zob[hk & 0xFFu], a.n_buckets);
           pstarted = true;
         }
         uint32_t slot = 0;
@@ -917,6 +931,7 @@ __device__ __forceinline__ void run_block(const BlockTask &a, uint8_t *lds) {
         const bool owner = hstat == 1 && !lane_empty && npop < K && tk[0] == win;
         if (owner) store_entry(table + pslot, NP, e32);
         P = NP;
+        hP ^= zob[jm1];
         E += dE;
         if (E < bestE) { bestE = E; bestP = P; }
         h = mix64(h ^ (((uint64_t)(jm1 + 1u) << 32) | (uint64_t)(uint32_t)E));
