@@ -41,15 +41,22 @@ def planes_of(nw: int, w: int) -> int:
     return 1 + b
 
 
-def ops_per_candidate(L: int) -> float:
-    """Algorithmic 32-bit lane-ops of one neighbour evaluation in the
-    bit-sliced form, averaged over the D candidates: one 3-input bitwise op
-    and one popcount per C plane word whose lag word holds at least one lag of
-    the candidate's forward range, the same for its backward range, and one
-    pair per word of the squared term.  Words outside a candidate's lag range
-    are not counted (the kernel skips them)."""
+# Plane caps reported per scan by the walk kernel, in the order of cap_steps.
+CAPS = (4, 5, 6, 0)
+
+
+def ops_per_scan(L: int, cap: int = 0) -> int:
+    """Algorithmic 32-bit lane-ops of one neighbourhood scan (all D candidates)
+    in the bit-sliced form: one 3-input bitwise op and one popcount per C
+    plane word whose lag word holds at least one lag of the candidate's
+    forward range, the same for its backward range, and one pair per word of
+    the squared term.  Words outside a candidate's lag range are not counted
+    (the kernel skips them).  cap > 0: every lag word is evaluated on `cap`
+    planes (exact while every c_t fits in cap bits); cap = 0: on the stored
+    per-word plane counts."""
     D, m = (L + 1) // 2, (L - 1) // 2
     nw = lag_words(L)
+    pl = [planes_of(nw, w) if cap == 0 else min(cap, planes_of(nw, w)) for w in range(nw)]
     tot = 0
     for j in range(1, D + 1):
         nc = D if j & 1 else m
@@ -57,9 +64,13 @@ def ops_per_candidate(L: int) -> float:
         nF = nc - 1 - r if j < D else 0
         nB = r
         fw, bw, q = (nF + 31) // 32, (nB + 31) // 32, (min(nF, nB) + 31) // 32
-        tot += 2 * (sum(planes_of(nw, w) for w in range(fw)) +
-                    sum(planes_of(nw, w) for w in range(bw)) + q)
-    return tot / D
+        tot += 2 * (sum(pl[:fw]) + sum(pl[:bw]) + q)
+    return tot
+
+
+def ops_per_candidate(L: int) -> float:
+    """Uncapped algorithmic lane-ops per neighbour evaluation (average over j)."""
+    return ops_per_scan(L, 0) / ((L + 1) // 2)
 
 
 def kernel_source_tag() -> str:
@@ -213,7 +224,7 @@ def main():
         del src_t, dst_t
 
     def one_step(seed):
-        return labs.walks(L, n, walk_len, seed=seed, plan=plan, workspace=ws)
+        return labs.walks(L, n, walk_len, seed=seed, plan=plan, workspace=ws, cap_steps=True)
 
     for w in range(args.warmup):
         one_step(1000 + w)
@@ -229,16 +240,20 @@ def main():
         ev0.record(stream)
         res = one_step(s)
         ev1.record(stream)
-        results.append(res["steps_done"])
+        results.append((res["steps_done"], res["cap_steps"]))
         ev1.synchronize()
         kernel_ms += ev0.elapsed_time(ev1)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    total_steps = int(sum(int(r.sum().item()) for r in results))
+    total_steps = int(sum(int(r[0].sum().item()) for r in results))
+    cap_scans = [int(sum(int(r[1][:, k].sum().item()) for r in results)) for k in range(4)]
+    scans = sum(cap_scans)
 
     steps_per_s = total_steps / wall
     avg_launch_s = kernel_ms / 1e3 / (args.steps * launches)
-    alg_ops_per_launch = (total_steps / (args.steps * launches)) * D * ops_per_candidate(L)
+    # algorithmic work: every scan priced at the plane count it needed
+    alg_ops = sum(c * ops_per_scan(L, cap) for c, cap in zip(cap_scans, CAPS))
+    alg_ops_per_launch = alg_ops / (args.steps * launches)
     achieved = alg_ops_per_launch / avg_launch_s
     tag = f"walk_kernel<NW={lag_words(L)},G={args.lanes}>@{kernel_source_tag()}"
     traffic = load_counter_traffic(tag)
@@ -267,7 +282,9 @@ def main():
                      "unit": "TOP/s", "frac": achieved / INT32_VALU_PEAK, "traffic": traffic,
                      "kernel": tag, "avg_launch_ms": avg_launch_s * 1e3,
                      "alg_ops_per_launch": alg_ops_per_launch,
-                     "ops_per_neighbour_eval": ops_per_candidate(L)},
+                     "ops_per_neighbour_eval": alg_ops / max(scans * D, 1),
+                     "ops_per_neighbour_eval_uncapped": ops_per_candidate(L),
+                     "scans_by_plane_cap": {str(c or "all"): v for c, v in zip(CAPS, cap_scans)}},
     }
     del ws
     torch.cuda.empty_cache()

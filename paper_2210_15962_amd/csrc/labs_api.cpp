@@ -220,6 +220,7 @@ int32_t labs_walks(const uint64_t *starts, int32_t L, int64_t n_walks, int64_t w
     w.trace_j = out->trace_j;
     w.trace_E = out->trace_E;
     w.n_trace = out->n_trace;
+    w.cap_steps = out->cap_steps;
     w.tables = static_cast<uint8_t *>(workspace);
     w.table_bytes = p.table_bytes;
     w.n_buckets = p.n_buckets;
@@ -292,6 +293,8 @@ int32_t plan_batch(const labs_instance *in, int32_t n_inst, BatchPlan &bp) {
     if (x.n_walks < 0) return fail(LABS_EINVAL, "instance %d: n_walks < 0", i);
     if (x.n_walks > 0 && (!x.out.best_seq || !x.out.best_E || !x.out.steps_done))
       return fail(LABS_EINVAL, "instance %d: best_seq, best_E and steps_done are required", i);
+    if (x.out.cap_steps)
+      return fail(LABS_EINVAL, "instance %d: cap_steps is reported by labs_walks only", i);
     if (x.out.n_trace < 0 || x.out.n_trace > x.n_walks)
       return fail(LABS_EINVAL, "instance %d: n_trace out of range", i);
     if (x.out.n_trace > 0 && (!x.out.trace_j || !x.out.trace_E))

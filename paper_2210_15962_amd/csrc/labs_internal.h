@@ -32,6 +32,7 @@ struct WalkLaunch {
   int16_t *trace_j;
   int32_t *trace_E;
   int64_t n_trace;
+  uint32_t *cap_steps;      // [n][4] scans per plane cap, or nullptr
   uint8_t *tables;          // chunk's visited tables, n_walks * table_bytes
   uint64_t table_bytes;     // bytes per walk (n_buckets * kBucketBytes)
   uint32_t n_buckets;

@@ -171,7 +171,7 @@ enum : int {
   DS_SPOS = 5,   // bit position of s_j in that word
   DS_KC = 6,     // (((2N - 4|MF & MB| + kBias) << 8) | (j - 1)) + 1; dead rows: 0
   DS_N = 7,      // (N - 2 sum_w 2^(B_w - 1) (|MF_w| + |MB_w|)) << 8, two's complement
-  DS_JM1 = 8,    // j - 1
+  DS_N8 = 8,     // N << 8 (planes-capped evaluation, see eval_key)
   DS_MASKS = 9   // MF[NW], MB[NWB], MFB[NWB]
 };
 
@@ -235,7 +235,7 @@ __device__ __forceinline__ void build_descriptors(uint32_t *desc, int L) {
     const int N = cntF + cntB;
     row[DS_KC] = (((uint32_t)(2 * N - 4 * cntFB + kBias) << 8) | (uint32_t)(j - 1)) + 1u;
     row[DS_N] = (uint32_t)(N - 2 * signw) << 8;
-    row[DS_JM1] = (uint32_t)(j - 1);
+    row[DS_N8] = (uint32_t)N << 8;
 #pragma unroll
     for (int i = DS_MASKS + NW + 2 * Gm::NWB; i < Gm::DESC; ++i) row[i] = 0;
   }
@@ -252,7 +252,6 @@ struct CandVec {
   uint32_t mb[Geom<NW>::NWB];
   uint32_t mfb[Geom<NW>::NWB];
   uint32_t sbit;
-  uint32_t jm1;
 };
 
 // Loads candidate j's descriptor row and neighbour vectors.  Only the first
@@ -264,7 +263,6 @@ __device__ __forceinline__ void load_candidate(const uint32_t *desc_row, const u
   using Gm = Geom<NW>;
   const uint4 d0 = *reinterpret_cast<const uint4 *>(desc_row);
   const uint4 d1 = *reinterpret_cast<const uint4 *>(desc_row + 4);
-  cv.jm1 = desc_row[DS_JM1];
   const uint32_t *fsrc = reinterpret_cast<const uint32_t *>(lds + colbase + d0.x);
   const uint32_t *bsrc = reinterpret_cast<const uint32_t *>(lds + colbase + d0.z);
   const uint32_t sw = *reinterpret_cast<const uint32_t *>(lds + colbase + d1.x);
@@ -309,12 +307,19 @@ __device__ __forceinline__ void load_candidate(const uint32_t *desc_row, const u
 // |M| - popcount(...) is taken instead, so every plane enters the Horner sum
 // with a positive weight and the |M| 2^(B_w - 1) excess is a per-candidate
 // constant folded into the descriptor (DS_N).
-template <int NW, int FW, int BW>
+//
+// With BP > 0 every lag word is evaluated on its low BP planes only.  This
+// is exact when every c_t of the walk fits in BP bits (two's complement), i.e.
+// when the stored planes BP-1 and above of every lag word are copies of plane
+// BP-1; the caller checks that for every walk of the wave.  Then plane BP-1
+// is the sign plane of every word and enters with weight -2^(BP-1).
+template <int NW, int FW, int BW, int BP>
 __device__ __forceinline__ uint32_t eval_key(const uint32_t *row, const uint8_t *lds,
                                              uint32_t colbase, const uint32_t *P) {
   using Gm = Geom<NW>;
   static_assert(FW >= 1 && FW <= NW && BW <= Gm::NWB && BW <= FW, "lag-word counts");
-  constexpr int BM = Gm::BMAX;
+  static_assert(BP == 0 || (BP >= 2 && BP <= planes_of(NW, NW - 1)), "plane cap");
+  constexpr int BM = BP > 0 ? BP : Gm::BMAX;
   const uint4 d0 = *reinterpret_cast<const uint4 *>(row);
   const uint4 d1 = *reinterpret_cast<const uint4 *>(row + 4);
   const uint32_t *fsrc = reinterpret_cast<const uint32_t *>(lds + colbase + d0.x);
@@ -346,27 +351,65 @@ __device__ __forceinline__ uint32_t eval_key(const uint32_t *row, const uint8_t 
   uint32_t q = 0u;
   static_for<0, FW>([&](auto wc) {
     constexpr int w = decltype(wc)::value;
-    constexpr int Bw = planes_of(NW, w), off = plane_off(NW, w);
+    constexpr int off = plane_off(NW, w);
+    constexpr int Bw = BP > 0 ? BP : planes_of(NW, w);
     const uint32_t mf = row[DS_MASKS + w];
 #pragma unroll
     for (int b = 0; b < Bw - 1; ++b) cnt[b] = popc_add((P[off + b] ^ fv[w]) & mf, cnt[b]);
-    cnt[Bw - 1] = popc_add(~(P[off + Bw - 1] ^ fv[w]) & mf, cnt[Bw - 1]);
+    if constexpr (BP > 0)
+      cnt[Bw - 1] = popc_add((P[off + Bw - 1] ^ fv[w]) & mf, cnt[Bw - 1]);
+    else
+      cnt[Bw - 1] = popc_add(~(P[off + Bw - 1] ^ fv[w]) & mf, cnt[Bw - 1]);
     if constexpr (w < BW) {
       const uint32_t mb = row[DS_MASKS + NW + w];
 #pragma unroll
       for (int b = 0; b < Bw - 1; ++b) cnt[b] = popc_add((P[off + b] ^ bv[w]) & mb, cnt[b]);
-      cnt[Bw - 1] = popc_add(~(P[off + Bw - 1] ^ bv[w]) & mb, cnt[Bw - 1]);
+      if constexpr (BP > 0)
+        cnt[Bw - 1] = popc_add((P[off + Bw - 1] ^ bv[w]) & mb, cnt[Bw - 1]);
+      else
+        cnt[Bw - 1] = popc_add(~(P[off + Bw - 1] ^ bv[w]) & mb, cnt[Bw - 1]);
       q = popc_add(~(fv[w] ^ bv[w]) & row[DS_MASKS + NW + Gm::NWB + w], q);   // |MFB| - q
     }
   });
-  uint32_t H = cnt[BM - 1];
+  uint32_t H;
+  uint32_t nconst;
+  if constexpr (BP > 0) {
+    H = 0u - cnt[BM - 1];                        // sign plane: weight -2^(BP-1)
+    nconst = row[DS_N8];                         // N << 8
+  } else {
+    H = cnt[BM - 1];                             // complemented sign planes
+    nconst = d1.w;                               // (N - 2 Kc) << 8
+  }
 #pragma unroll
   for (int b = BM - 2; b >= 0; --b) H = lshl_add<1>(H, cnt[b]);
-  const uint32_t t = lshl_add<9>(H, d1.w);      // (2 X + N) << 8
+  const uint32_t t = lshl_add<9>(H, nconst);    // (2 X + N) << 8
   const uint32_t kq = lshl_add<11>(q, d1.z);    // (((kc - 8 q) << 8) | (j - 1)) + 1
   // s_j = -1 (bit set, sg = ~0): kq - 1 + t; else kq + ~t = kq - 1 - t.
   const uint32_t sg = (uint32_t)__builtin_amdgcn_sbfe((int)sw, (int)d1.y, 1);
   return kq + sg + ~(t ^ sg);
+}
+
+// Smallest plane cap in {4, 5, 6} valid for every active walk of the wave
+// (0: none, use the per-word plane counts).  A cap BP is valid for a lane when
+// the planes BP..B_w-1 of every lag word equal plane BP-1.
+template <int NW>
+__device__ __forceinline__ int wave_plane_cap(const uint32_t *P, bool active) {
+  uint32_t d4 = 0u, d5 = 0u, d6 = 0u;   // OR of plane differences at b = 4, 5, >= 6
+  static_for<0, NW>([&](auto wc) {
+    constexpr int w = decltype(wc)::value;
+    constexpr int off = plane_off(NW, w), Bw = planes_of(NW, w);
+#pragma unroll
+    for (int b = 4; b < Bw; ++b) {
+      const uint32_t d = P[off + b] ^ P[off + b - 1];
+      if (b == 4) d4 |= d;
+      else if (b == 5) d5 |= d;
+      else d6 |= d;
+    }
+  });
+  if (__ballot(active && d6 != 0u) != 0ull) return 0;
+  if (__ballot(active && d5 != 0u) != 0ull) return 6;
+  if (__ballot(active && d4 != 0u) != 0ull) return 5;
+  return 4;
 }
 
 // Lag words some candidate of iteration i (j = G*i + 1 .. G*i + G) needs:
@@ -575,6 +618,7 @@ struct BlockTask {
   int16_t *trace_j;
   int32_t *trace_E;
   int64_t n_trace;
+  uint32_t *cap_steps;      // [walk][4] scans per plane cap (4, 5, 6, none), or nullptr
   uint8_t *tables;          // visited table of slot s at tables + s * table_bytes
   uint64_t table_bytes;
   uint32_t n_buckets;
@@ -744,6 +788,9 @@ __device__ __forceinline__ void run_block(const BlockTask &a, uint8_t *lds) {
   const int ncand = (D - r + Gl - 1) / Gl;       // may be 0 for r >= D
   const int nruns = (int)__builtin_amdgcn_readfirstlane(runs[kRunSlots - 1]);
   constexpr uint64_t kMask = WordsMask<NW, G>::value;
+  // Scans per plane cap (walk kernel only; batches do not report them).
+  constexpr bool kCountCaps = G > 0;
+  uint32_t ncap4 = 0u, ncap5 = 0u, ncap6 = 0u, ncap0 = 0u;
   const bool tracing = active && walk < a.n_trace;
 
   // Every walk still moving has made exactly step_begin moves (trapped walks
@@ -774,9 +821,19 @@ __device__ __forceinline__ void run_block(const BlockTask &a, uint8_t *lds) {
     bool done = !active;
     uint32_t win = kKeyMax;
 
-    // (0) main scan: every local candidate goes into the top-K.
+    // (0) main scan: every local candidate goes into the top-K, evaluated on
+    //     as few C planes as the wave's current C values allow.
 #pragma unroll
     for (int i = 0; i < K; ++i) tk[i] = kKeyMax;
+    const int bp = wave_plane_cap<NW>(Pl, active);
+    if constexpr (kCountCaps) {
+      if (active) {
+        ncap4 += bp == 4 ? 1u : 0u;
+        ncap5 += bp == 5 ? 1u : 0u;
+        ncap6 += bp == 6 ? 1u : 0u;
+        ncap0 += bp == 0 ? 1u : 0u;
+      }
+    }
 #pragma unroll 1
     for (int sr = 0; sr < nruns; ++sr) {
       const uint32_t e0 = __builtin_amdgcn_readfirstlane(runs[sr]);
@@ -784,12 +841,19 @@ __device__ __forceinline__ void run_block(const BlockTask &a, uint8_t *lds) {
       const int ie = (int)(__builtin_amdgcn_readfirstlane(runs[sr + 1]) >> 8);
       with_words<NW, kMask>((int)(e0 & 0xFFu), [&](auto Fc, auto Bc) __attribute__((always_inline)) {
         constexpr int F = decltype(Fc)::value, B = decltype(Bc)::value;
+        auto scan = [&](auto BPc) __attribute__((always_inline)) {
+          constexpr int BPv = decltype(BPc)::value;
 #pragma unroll 1
-        for (int i = ib; i < ie; ++i) {
-          // j > D reads a dead row whose key ~0 leaves the top-K unchanged
-          const int j = r + 1 + Gl * i;
-          topk_insert<K>(tk, eval_key<NW, F, B>(desc + (j - 1) * Gm::DESC, cols, colbase, Pl));
-        }
+          for (int i = ib; i < ie; ++i) {
+            // j > D reads a dead row whose key ~0 leaves the top-K unchanged
+            const int j = r + 1 + Gl * i;
+            topk_insert<K>(tk, eval_key<NW, F, B, BPv>(desc + (j - 1) * Gm::DESC, cols, colbase, Pl));
+          }
+        };
+        if (bp == 4) scan(std::integral_constant<int, 4>{});
+        else if (bp == 5) scan(std::integral_constant<int, 5>{});
+        else if (bp == 6) scan(std::integral_constant<int, 6>{});
+        else scan(std::integral_constant<int, 0>{});
       });
     }
     // The predecessor is visited: drop it from its owner's top-K.
@@ -834,7 +898,7 @@ __device__ __forceinline__ void run_block(const BlockTask &a, uint8_t *lds) {
               if ((i & 63) == 0) xw = ex_word(i >> 6);
               const bool live = scanning && i < ncand;
               const int j = r + 1 + Gl * i;             // j > D: dead row
-              uint32_t key = eval_key<NW, F, B>(desc + (j - 1) * Gm::DESC, cols, colbase, Pl);
+              uint32_t key = eval_key<NW, F, B, 0>(desc + (j - 1) * Gm::DESC, cols, colbase, Pl);
               key |= 0u - (uint32_t)(xw & 1ull);
               xw >>= 1;
               if (live) topk_insert<K>(tk, key);
@@ -957,6 +1021,13 @@ __device__ __forceinline__ void run_block(const BlockTask &a, uint8_t *lds) {
     o.trapped = trapped ? 1u : 0u;
     a.state[walk] = o;
   }
+  if constexpr (kCountCaps) {
+    if (a.cap_steps && slot < a.n_walks && r == 0) {
+      uint4 v;
+      v.x = ncap4; v.y = ncap5; v.z = ncap6; v.w = ncap0;
+      *reinterpret_cast<uint4 *>(a.cap_steps + (uint64_t)walk * 4u) = v;
+    }
+  }
   if (finished && slot < a.n_walks && r == 0) {
     a.best_seq[walk * KW] = bestP.w0;
     if (KW > 1) a.best_seq[walk * KW + 1] = bestP.w1;
@@ -989,6 +1060,7 @@ __global__ void __launch_bounds__(kBlock) walk_kernel(const WalkLaunch w) {
   t.tables = w.tables + (uint64_t)first * w.table_bytes;
   t.table_bytes = w.table_bytes;
   t.n_buckets = w.n_buckets;
+  t.cap_steps = w.cap_steps;
   t.state = nullptr;
   t.step_begin = 0;
   t.step_end = w.walk_len;
@@ -1029,6 +1101,7 @@ __global__ void __launch_bounds__(kBlock) batch_kernel(const BatchLaunch b) {
     t.trace_j = in.trace_j;
     t.trace_E = in.trace_E;
     t.n_trace = in.n_trace;
+    t.cap_steps = nullptr;
     t.tables = in.tables ? in.tables + (uint64_t)item.walk_begin * in.table_bytes : arena;
     t.table_bytes = in.table_bytes;
     t.n_buckets = in.n_buckets;

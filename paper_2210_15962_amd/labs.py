@@ -37,7 +37,7 @@ class LabsError(RuntimeError):
 
 class WalkOut(ctypes.Structure):
     _fields_ = [("best_seq", VP), ("best_E", VP), ("steps_done", VP), ("digest", VP),
-                ("trace_j", VP), ("trace_E", VP), ("n_trace", I64)]
+                ("trace_j", VP), ("trace_E", VP), ("n_trace", I64), ("cap_steps", VP)]
 
 
 class Plan(ctypes.Structure):
@@ -233,12 +233,13 @@ def alloc_workspace(nbytes: int, device="cuda"):
 
 def walks(L: int, n_walks: int, walk_len: int, seed: int = 0, starts_t=None, n_trace: int = 0,
           plan: Optional[Plan] = None, workspace=None, digest: bool = True, stream=None,
-          device="cuda"):
+          device="cuda", cap_steps: bool = False):
     """Run n_walks self-avoiding walks; returns a dict of CUDA tensors.
 
     Keys: best_seq int64 [n, W] (bit patterns of the uint64 key words), best_E
-    int32 [n], steps_done int64 [n], digest int64 [n] (uint64 bit patterns), and
-    trace_j int16 / trace_E int32 [n_trace, walk_len] when n_trace > 0.
+    int32 [n], steps_done int64 [n], digest int64 [n] (uint64 bit patterns),
+    trace_j int16 / trace_E int32 [n_trace, walk_len] when n_trace > 0, and
+    cap_steps int32 [n, 4] (scans on 4, 5, 6 or all C planes) when requested.
     """
     import torch
     W = key_words(L)
@@ -259,9 +260,11 @@ def walks(L: int, n_walks: int, walk_len: int, seed: int = 0, starts_t=None, n_t
     if n_trace:
         res["trace_j"] = torch.zeros((n_trace, walk_len), dtype=torch.int16, device=device)
         res["trace_E"] = torch.zeros((n_trace, walk_len), dtype=torch.int32, device=device)
+    if cap_steps:
+        res["cap_steps"] = torch.zeros((n_walks, 4), dtype=torch.int32, device=device)
     out = WalkOut(_dptr(res["best_seq"]), _dptr(res["best_E"]), _dptr(res["steps_done"]),
                   _dptr(res["digest"]), _dptr(res.get("trace_j")), _dptr(res.get("trace_E")),
-                  n_trace)
+                  n_trace, _dptr(res.get("cap_steps")))
     _check(lib().labs_walks(_dptr(starts_t), L, n_walks, walk_len, seed & 0xFFFFFFFFFFFFFFFF,
                             ctypes.byref(out), _dptr(workspace), workspace.numel(),
                             ctypes.byref(plan) if plan else None, _stream_handle(stream)))

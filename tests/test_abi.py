@@ -162,3 +162,14 @@ def test_serve_validation_before_any_device_call():
     assert lib.labs_serve_wait(None, 1, 0, None) == labs.LABS_EINVAL
     assert lib.labs_serve_stats(None, None) == labs.LABS_EINVAL
     assert lib.labs_serve_destroy(None) == labs.LABS_OK
+
+
+def test_batch_rejects_cap_counts():
+    lib = labs.lib()
+    out = {"best_seq": None, "best_E": None, "steps_done": None, "digest": None}
+    arr = labs.make_instances([dict(L=27, n_walks=4, walk_len=10)], [out])
+    arr[0].out.best_seq = arr[0].out.best_E = arr[0].out.steps_done = 1
+    arr[0].out.cap_steps = 1
+    ws = ctypes.c_void_p(1)
+    assert lib.labs_walks_batch(arr, 1, ws, 1 << 30, None) == labs.LABS_EINVAL
+    assert b"cap_steps" in lib.labs_last_error()

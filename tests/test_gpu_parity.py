@@ -224,3 +224,25 @@ def test_best_sequence_energy_recomputed():
         assert O.energy_packed(best[i], L) == int(E[i])
     m = (L - 1) // 2
     assert ((E - m) % 8 == 0).all() and (E >= m).all()
+
+
+@pytest.mark.parametrize("G", [1, 4])
+@pytest.mark.parametrize("L,steps,n", [(7, 200, 64), (27, 2000, 128), (151, 2500, 256), (301, 600, 64)])
+def test_plane_cap_counts(L, steps, n, G):
+    """Scans per plane cap: one per move plus one for a trapped walk's last
+    scan; asking for the counts changes no result; the oracle agrees."""
+    labs = _labs()
+    keys = I.random_start_keys(L, n, seed=L + G)
+    st = torch.from_numpy(I.as_int64_keys(keys)).cuda()
+    plan = labs.make_plan(lanes_per_walk=G)
+    a = labs.walks(L, n, steps, starts_t=st, plan=plan, cap_steps=True)
+    b = labs.walks(L, n, steps, starts_t=st, plan=plan)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(_u64(a["digest"]), _u64(b["digest"]))
+    done = a["steps_done"].cpu().numpy()
+    caps = a["cap_steps"].cpu().numpy().astype(np.int64)
+    np.testing.assert_array_equal(caps.sum(1), done + (done < steps))
+    assert_matches_oracle(L, keys, steps, a)
+    if L >= 27:
+        # walks settle where C is small: most scans run on capped planes
+        assert caps[:, :3].sum() > 0.5 * caps.sum()
