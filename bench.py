@@ -125,25 +125,43 @@ def serve_workload(n_req: int, rate: float, seed: int = 0):
             for i, L in enumerate(Ls)]
 
 
-def run_serving(n_req: int, rate: float, load_factor: float, chunk: int, pool_frac: float = 0.85):
-    """Serve the stream through labs_serve_* and run the same requests as one
-    plain mixed-L batch; returns latency percentiles and both throughputs."""
-    import numpy as np
+def run_plain_batch(n_req: int, load_factor: float):
+    """The served stream's requests as one plain mixed-L batch (one persistent
+    launch); the workspace is allocated before the timed region."""
+    import ctypes
     import torch
     from paper_2210_15962_amd import labs
-    reqs = serve_workload(n_req, rate)
-    # the same requests as one plain batch (one persistent launch), timed first
+    reqs = serve_workload(n_req, 1.0)
     specs = [dict(L=q["L"], n_walks=q["n_walks"], walk_len=q["walk_len"], seed=q["seed"],
                   load_factor=load_factor) for q in reqs]
+    outs = [labs._alloc_outputs(sp["L"], sp["n_walks"], sp["walk_len"], 0) for sp in specs]
+    nb = labs.U64(0)
+    labs._check(labs.lib().labs_batch_workspace_bytes(labs.make_instances(specs, outs), len(specs),
+                                                      ctypes.byref(nb)))
+    ws = labs.alloc_workspace(nb.value)
+    del outs
     torch.cuda.synchronize()
     tb = time.perf_counter()
-    out = labs.walks_batch(specs)
+    out = labs.walks_batch(specs, workspace=ws)
     torch.cuda.synchronize()
     tb = time.perf_counter() - tb
     bsteps = int(sum(int(o["steps_done"].sum().item()) for o in out))
     bdig = [o["digest"].cpu().numpy() for o in out]
-    del out
+    del out, ws
     torch.cuda.empty_cache()
+    return bsteps / tb, bsteps, bdig
+
+
+def run_serving(n_req: int, rate: float, load_factor: float, chunk: int, batch=None,
+                pool_frac: float = 0.85):
+    """Serve the stream through labs_serve_* (Poisson arrivals at `rate`) and
+    compare with the same requests as one plain batch; returns latency
+    percentiles and both throughputs."""
+    import numpy as np
+    import torch
+    from paper_2210_15962_amd import labs
+    reqs = serve_workload(n_req, rate)
+    batch_rate, bsteps, bdig = batch if batch is not None else run_plain_batch(n_req, load_factor)
     free, _ = torch.cuda.mem_get_info()
     pool = int(free * pool_frac)
     with labs.Server(pool_bytes=pool, load_factor=load_factor, chunk_steps=chunk) as srv:
@@ -165,10 +183,10 @@ def run_serving(n_req: int, rate: float, load_factor: float, chunk: int, pool_fr
             "moves_per_walk": 65536, "L_range": [121, 301], "chunk_steps": chunk,
             "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
             "served_steps_per_s": served, "served_busy_steps_per_s": steps / (st["busy_ns"] / 1e9),
-            "batch_steps_per_s": bsteps / tb, "served_over_batch": served / (bsteps / tb),
+            "batch_steps_per_s": batch_rate, "served_over_batch": served / batch_rate,
             "launches": st["launches"], "pool_gib": st["pool_bytes"] / 2**30,
             "pool_peak_gib": st["pool_peak"] / 2**30,
-            "offered_over_capacity": rate * 4096 * 65536 / (bsteps / tb),
+            "offered_over_capacity": rate * 4096 * 65536 / batch_rate,
             "served_equals_batch": bool(same and steps == bsteps)}
 
 
@@ -184,9 +202,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibration-copy-mib", type=int, default=0,
                     help="run one plain device copy of this size first (counter calibration)")
-    ap.add_argument("--serve-requests", type=int, default=24)
+    ap.add_argument("--serve-requests", type=int, default=64)
     ap.add_argument("--serve-rate", type=float, default=10.0)
-    ap.add_argument("--serve-chunk", type=int, default=8192)
+    ap.add_argument("--serve-chunk", type=int, default=4096)
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--serve-sweep", type=str, default="",
                     help="comma-separated arrival rates: serve only, one JSON line per rate")
@@ -201,9 +219,10 @@ def main():
     from paper_2210_15962_amd import labs
 
     if args.serve_sweep:
+        batch = run_plain_batch(args.serve_requests, args.load_factor)
         for rate in [float(x) for x in args.serve_sweep.split(",")]:
-            print(json.dumps(run_serving(args.serve_requests, rate, args.load_factor, args.serve_chunk)),
-                  flush=True)
+            print(json.dumps(run_serving(args.serve_requests, rate, args.load_factor, args.serve_chunk,
+                                         batch=batch)), flush=True)
         return
 
     L, n = WORKLOAD["L"], WORKLOAD["n_walks"]

@@ -245,8 +245,9 @@ typedef struct labs_server labs_server;
 typedef struct labs_serve_cfg {
   uint64_t pool_bytes;     /* device pool (allocated once by create); 0 = 50% of free memory */
   int32_t max_pending;     /* host queue capacity; 0 = 4096 */
-  int32_t lanes_per_walk;  /* 2, 4 or 8; 0 = tuned table / default */
-  int64_t chunk_steps;     /* moves per launch per request; 0 = 8192 */
+  int32_t lanes_per_walk;  /* 2, 4 or 8; 0 = per launch, 4 or 8, whichever fills the
+                              resident workgroups in whole rounds better */
+  int64_t chunk_steps;     /* moves per launch per request; 0 = 4096 */
   double load_factor;      /* visited-table load factor; 0 = default 0.5 */
 } labs_serve_cfg;
 

@@ -325,11 +325,11 @@ int32_t plan_batch(const labs_instance *in, int32_t n_inst, BatchPlan &bp) {
     bp.arena_bytes = std::max(bp.arena_bytes, (uint64_t)per_block * p.table_bytes);
     order.push_back(Ord{nw, lp.lanes_per_walk, x.L, i});
   }
-  // Items of similar shape run back to back (same code path and table size).
+  // Longest items first (cost grows with L): the persistent grid then ends
+  // on short items, which keeps the tail of the launch short.
   std::stable_sort(order.begin(), order.end(), [](const Ord &a, const Ord &b) {
-    if (a.nw != b.nw) return a.nw < b.nw;
-    if (a.G != b.G) return a.G < b.G;
-    return a.L < b.L;
+    if (a.L != b.L) return a.L > b.L;
+    return a.G < b.G;
   });
   for (const Ord &o : order) {
     const int per_block = lsaw::kBlock / o.G;

@@ -152,8 +152,8 @@ uint64_t footprint(Request &q) {
   return o;
 }
 
-int64_t items_of(const Request &q) {
-  const int per = lsaw::kBlock / q.lanes;
+int64_t items_of(const Request &q, int lanes) {
+  const int per = lsaw::kBlock / lanes;
   return (q.n_walks + per - 1) / per;
 }
 
@@ -181,11 +181,11 @@ void run_worker(labs_server *s) {
     {
       std::unique_lock<std::mutex> lk(s->mu);
       int64_t n_items = 0;
-      for (Request *q : s->active) n_items += items_of(*q);
+      for (Request *q : s->active) n_items += items_of(*q, 8);
       // first come, first served: the head waits until its footprint fits
       while (!s->pending.empty() && !s->stop) {
         Request *q = s->pending.front();
-        if ((int64_t)s->active.size() + 1 > kMaxInst || n_items + items_of(*q) > kMaxItems) break;
+        if ((int64_t)s->active.size() + 1 > kMaxInst || n_items + items_of(*q, 8) > kMaxItems) break;
         uint64_t off = 0;
         if (!s->ranges.alloc(q->bytes, &off)) break;
         q->off = off;
@@ -194,7 +194,7 @@ void run_worker(labs_server *s) {
         q->upload = !q->starts.empty();
         s->pending.pop_front();
         s->active.push_back(q);
-        n_items += items_of(*q);
+        n_items += items_of(*q, 8);
         s->st.admitted++;
       }
       s->st.pool_used = s->ranges.used();
@@ -211,6 +211,24 @@ void run_worker(labs_server *s) {
     items.clear();
     budget.clear();
     int nw_max = 1;
+    for (Request *q : run) nw_max = std::max(nw_max, lsaw::lag_words_for(q->L));
+    const int variant = lsaw::batch_variant(nw_max);
+    int per_cu = 1, cus = 256;
+    (void)lsaw::batch_blocks_per_cu(variant, &per_cu);
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, s->device);
+    const int64_t slots = (int64_t)std::max(per_cu, 1) * cus;
+    // Lanes per walk for this launch (walk state and tables do not depend on
+    // it): a request's own choice if it has one, else 4 or 8, whichever
+    // fills the resident workgroups in whole rounds better (8 lanes cost
+    // about 20% more per walk step than 4: the per-move work is shared by
+    // half as many candidates per lane).
+    int64_t items4 = 0;
+    for (Request *q : run) items4 += items_of(*q, 4);
+    auto fill = [&](int64_t n) {
+      const int64_t rounds = (n + slots - 1) / slots;
+      return rounds > 0 ? (double)n / (double)(rounds * slots) : 0.0;
+    };
+    const int auto_lanes = 0.8 * fill(2 * items4) > fill(items4) ? 8 : 4;
     for (size_t k = 0; k < run.size(); ++k) {
       Request *q = run[k];
       uint8_t *b = s->pool + s->ctl_bytes + q->off;
@@ -241,22 +259,22 @@ void run_worker(labs_server *s) {
       d.step_end = q->progress + take;
       d.resume = q->launched ? 1 : 0;
       inst.push_back(d);
-      nw_max = std::max(nw_max, lsaw::lag_words_for(q->L));
-      const int per = lsaw::kBlock / q->lanes;
+      const int lanes = q->lanes ? q->lanes : auto_lanes;
+      const int per = lsaw::kBlock / lanes;
       for (int64_t w = 0; w < q->n_walks; w += per) {
         lsaw::BatchItemDev it{};
         it.inst = (int32_t)k;
-        it.code = (lsaw::lag_words_for(q->L) << 4) | q->lanes;
+        it.code = (lsaw::lag_words_for(q->L) << 4) | lanes;
         it.n_walks = (int32_t)std::min<int64_t>(per, q->n_walks - w);
         it.walk_begin = w;
         items.push_back(it);
       }
     }
-    const int variant = lsaw::batch_variant(nw_max);
-    int per_cu = 1, cus = 256;
-    (void)lsaw::batch_blocks_per_cu(variant, &per_cu);
-    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, s->device);
-    const int grid = (int)std::min<int64_t>((int64_t)items.size(), (int64_t)std::max(per_cu, 1) * cus);
+    // longest items first (cost grows with L) keeps the launch's tail short
+    std::stable_sort(items.begin(), items.end(), [&](const lsaw::BatchItemDev &x, const lsaw::BatchItemDev &y) {
+      return inst[x.inst].L > inst[y.inst].L;
+    });
+    const int grid = (int)std::min<int64_t>((int64_t)items.size(), slots);
     uint8_t *ctl = s->pool;
     const uint64_t items_off = 256;
     const uint64_t inst_off = al(items_off + (uint64_t)kMaxItems * sizeof(lsaw::BatchItemDev));
@@ -351,7 +369,7 @@ int32_t labs_serve_create(const labs_serve_cfg *cfg, labs_server **server) {
   labs_server *s = new labs_server();
   s->max_pending = c.max_pending ? c.max_pending : 4096;
   s->lanes = c.lanes_per_walk;
-  s->chunk = c.chunk_steps ? c.chunk_steps : 8192;
+  s->chunk = c.chunk_steps ? c.chunk_steps : 4096;
   s->load_factor = c.load_factor != 0.0 ? c.load_factor : 0.0;
   hipError_t e = hipGetDevice(&s->device);
   size_t free_b = 0, total_b = 0;
@@ -396,14 +414,13 @@ int32_t labs_serve_submit(labs_server *s, int32_t L, int64_t n_walks, int64_t wa
                           const uint64_t *starts, uint64_t *req_id) {
   if (!s || !req_id) return lsaw::set_error(LABS_EINVAL, "NULL server or req_id");
   if (n_walks <= 0) return lsaw::set_error(LABS_EINVAL, "n_walks=%lld must be > 0", (long long)n_walks);
-  int32_t lanes = s->lanes;
+  const int32_t lanes = s->lanes;                 // 0: chosen per launch
   double lf = s->load_factor;
-  {
+  if (lf == 0.0) {
     int32_t tl = 4;
     double tf = 0.5;
     if (L >= 3 && L <= lsaw::kLMax && (L & 1)) lsaw::tuned_plan(L, &tl, &tf);
-    if (!lanes) lanes = (tl == 2 || tl == 4 || tl == 8) ? tl : 4;
-    if (lf == 0.0) lf = tf;
+    lf = tf;
   }
   uint32_t nb = 0;
   uint64_t tb = 0;
@@ -431,7 +448,7 @@ int32_t labs_serve_submit(labs_server *s, int32_t L, int64_t n_walks, int64_t wa
       }
   }
   q->bytes = footprint(*q);
-  if (q->bytes > s->pool_bytes - s->ctl_bytes || items_of(*q) > kMaxItems) {
+  if (q->bytes > s->pool_bytes - s->ctl_bytes || items_of(*q, 8) > kMaxItems) {
     const unsigned long long need = q->bytes;
     delete q;
     return lsaw::set_error(LABS_EINVAL, "request footprint %llu bytes exceeds the pool", need);
