@@ -190,6 +190,51 @@ def run_serving(n_req: int, rate: float, load_factor: float, chunk: int, batch=N
             "served_equals_batch": bool(same and steps == bsteps)}
 
 
+def run_mixed_batch(steps: int, warmup: int, autotune: bool):
+    """256 instances, L uniform odd in [61, 223], 1,024 walks x 32,768 moves
+    each, in one persistent launch captured in a hipGraph; replays timed with
+    HIP events.  With autotune, every distinct L is tuned first."""
+    import torch
+    import labs_inputs as I
+    from paper_2210_15962_amd import labs
+    Ls = [int(L) for L in I.odd_lengths(256, 61, 223, seed=0)]
+    specs = [dict(L=L, n_walks=1024, walk_len=32768, seed=i) for i, L in enumerate(Ls)]
+    tuned = {}
+    t_tune = 0.0
+    if autotune:
+        t0 = time.perf_counter()
+        for L in sorted(set(Ls)):
+            tuned[L] = labs.autotune(L)
+        t_tune = time.perf_counter() - t0
+    g = labs.BatchGraph(specs)
+    stream = torch.cuda.current_stream()
+    for _ in range(warmup):
+        g.launch()
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    total, ms = 0, 0.0
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ev0.record(stream)
+        res = g.launch()
+        ev1.record(stream)
+        ev1.synchronize()
+        ms += ev0.elapsed_time(ev1)
+        total += int(sum(int(r["steps_done"].sum().item()) for r in res))
+    wall = time.perf_counter() - t0
+    g.close()
+    lanes = {}
+    for L in Ls:
+        k = labs.tune_get(L)[0]
+        lanes[k] = lanes.get(k, 0) + 1
+    return {"workload": "256 instances, L uniform odd in [61, 223], 1024 walks x 32768 moves, "
+                        "one persistent launch per replay (hipGraph)",
+            "steps_per_s": total / wall, "ms_per_launch": ms / steps, "replays": steps,
+            "autotuned": autotune, "tune_seconds": t_tune,
+            "instances_by_lanes_per_walk": {str(k): v for k, v in sorted(lanes.items())},
+            "distinct_L": len(set(Ls))}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -208,6 +253,8 @@ def main():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--serve-sweep", type=str, default="",
                     help="comma-separated arrival rates: serve only, one JSON line per rate")
+    ap.add_argument("--mixed-batch", action="store_true",
+                    help="256-instance mixed-L batch (hipGraph replays) only, default then autotuned")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -217,6 +264,11 @@ def main():
 
     import torch
     from paper_2210_15962_amd import labs
+
+    if args.mixed_batch:
+        for tune in (False, True):
+            print(json.dumps(run_mixed_batch(args.steps, args.warmup, tune)), flush=True)
+        return
 
     if args.serve_sweep:
         batch = run_plain_batch(args.serve_requests, args.load_factor)

@@ -371,8 +371,12 @@ def tune_get(L: int):
     return int(g.value), float(lf.value), rc == LABS_OK
 
 
-def autotune(L: int, n_walks: int = 4096, walk_len: int = 1024, stream=None, device="cuda"):
-    """Time lanes per walk / load factor for L on a short run; stores and returns the best."""
+def autotune(L: int, n_walks: int = 131072, walk_len: int = 512, stream=None, device="cuda"):
+    """Time lanes per walk / load factor for L on a short run; stores and returns the best.
+
+    The run must fill the GPU at every candidate lane count (131,072 walks do
+    at 2 lanes per walk), otherwise it measures fill rather than cost per step.
+    """
     W = key_words(L)
     need = workspace_bytes(L, n_walks, walk_len, make_plan(2, 0.5)) + \
         ((n_walks * (8 * W + 12) + 255) // 256) * 256
