@@ -315,7 +315,7 @@ __device__ __forceinline__ void load_candidate(const uint32_t *desc_row, const u
 // is the sign plane of every word and enters with weight -2^(BP-1).
 template <int NW, int FW, int BW, int BP>
 __device__ __forceinline__ uint32_t eval_key(const uint32_t *row, const uint8_t *lds,
-                                             uint32_t colbase, const uint32_t *P) {
+                                             uint32_t colbase, const uint32_t *P, uint32_t sg) {
   using Gm = Geom<NW>;
   static_assert(FW >= 1 && FW <= NW && BW <= Gm::NWB && BW <= FW, "lag-word counts");
   static_assert(BP == 0 || (BP >= 2 && BP <= planes_of(NW, NW - 1)), "plane cap");
@@ -324,7 +324,6 @@ __device__ __forceinline__ uint32_t eval_key(const uint32_t *row, const uint8_t 
   const uint4 d1 = *reinterpret_cast<const uint4 *>(row + 4);
   const uint32_t *fsrc = reinterpret_cast<const uint32_t *>(lds + colbase + d0.x);
   const uint32_t *bsrc = reinterpret_cast<const uint32_t *>(lds + colbase + d0.z);
-  const uint32_t sw = *reinterpret_cast<const uint32_t *>(lds + colbase + d1.x);
   uint32_t fv[FW];
   uint32_t bv[BW > 0 ? BW : 1];
   {
@@ -384,8 +383,7 @@ __device__ __forceinline__ uint32_t eval_key(const uint32_t *row, const uint8_t 
   for (int b = BM - 2; b >= 0; --b) H = lshl_add<1>(H, cnt[b]);
   const uint32_t t = lshl_add<9>(H, nconst);    // (2 X + N) << 8
   const uint32_t kq = lshl_add<11>(q, d1.z);    // (((kc - 8 q) << 8) | (j - 1)) + 1
-  // s_j = -1 (bit set, sg = ~0): kq - 1 + t; else kq + ~t = kq - 1 - t.
-  const uint32_t sg = (uint32_t)__builtin_amdgcn_sbfe((int)sw, (int)d1.y, 1);
+  // sg = ~0 when s_j = -1: kq - 1 + t; else kq + ~t = kq - 1 - t.
   return kq + sg + ~(t ^ sg);
 }
 
@@ -786,6 +784,32 @@ __device__ __forceinline__ void run_block(const BlockTask &a, uint8_t *lds) {
 
   // Local candidates of lane r: j = r + 1 + Gl*i.
   const int ncand = (D - r + Gl - 1) / Gl;       // may be 0 for r >= D
+  const int lgG = Gl == 8 ? 3 : Gl == 4 ? 2 : Gl == 2 ? 1 : 0;
+  // Signs of the lane's candidates, bit i <-> s_{r+1+Gl*i} = -1 (0 past D),
+  // kept in registers: the scan reads s_j from here, the move toggles it.
+  constexpr int kGmin = G > 0 ? G : 2;
+  constexpr int kSW = ((Gm::DMAX + kGmin - 1) / kGmin + 31) / 32;
+  uint32_t smk[kSW];
+#pragma unroll
+  for (int w = 0; w < kSW; ++w) smk[w] = 0u;
+#pragma unroll 1
+  for (int i = 0; i < nmax; ++i) {
+    const int j = r + 1 + Gl * i;
+    const uint32_t bit = j <= D ? key_bit(P, j - 1) : 0u;
+    static_for<0, kSW>([&](auto wc) {
+      constexpr int w = decltype(wc)::value;
+      if ((i >> 5) == w) smk[w] |= bit << (i & 31);
+    });
+  }
+  auto sign_of = [&](int i) -> uint32_t {        // ~0 if s_j = -1, else 0 (i uniform)
+    // word select with masks (a select chain becomes a stack lookup table)
+    uint32_t wv = 0u;
+    static_for<0, kSW>([&](auto wc) {
+      constexpr int w = decltype(wc)::value;
+      wv |= smk[w] & (0u - (uint32_t)((i >> 5) == w));
+    });
+    return (uint32_t)__builtin_amdgcn_sbfe((int)wv, i & 31, 1);
+  };
   const int nruns = (int)__builtin_amdgcn_readfirstlane(runs[kRunSlots - 1]);
   constexpr uint64_t kMask = WordsMask<NW, G>::value;
   // Scans per plane cap (walk kernel only; batches do not report them).
@@ -847,7 +871,8 @@ __device__ __forceinline__ void run_block(const BlockTask &a, uint8_t *lds) {
           for (int i = ib; i < ie; ++i) {
             // j > D reads a dead row whose key ~0 leaves the top-K unchanged
             const int j = r + 1 + Gl * i;
-            topk_insert<K>(tk, eval_key<NW, F, B, BPv>(desc + (j - 1) * Gm::DESC, cols, colbase, Pl));
+            topk_insert<K>(tk, eval_key<NW, F, B, BPv>(desc + (j - 1) * Gm::DESC, cols, colbase, Pl,
+                                                       sign_of(i)));
           }
         };
         if (bp == 4) scan(std::integral_constant<int, 4>{});
@@ -898,7 +923,7 @@ __device__ __forceinline__ void run_block(const BlockTask &a, uint8_t *lds) {
               if ((i & 63) == 0) xw = ex_word(i >> 6);
               const bool live = scanning && i < ncand;
               const int j = r + 1 + Gl * i;             // j > D: dead row
-              uint32_t key = eval_key<NW, F, B, 0>(desc + (j - 1) * Gm::DESC, cols, colbase, Pl);
+              uint32_t key = eval_key<NW, F, B, 0>(desc + (j - 1) * Gm::DESC, cols, colbase, Pl, sign_of(i));
               key |= 0u - (uint32_t)(xw & 1ull);
               xw >>= 1;
               if (live) topk_insert<K>(tk, key);
@@ -996,6 +1021,13 @@ __device__ __forceinline__ void run_block(const BlockTask &a, uint8_t *lds) {
         if (owner) store_entry(table + pslot, NP, e32);
         P = NP;
         hP ^= zob[jm1];
+        if ((int)(jm1 & (uint32_t)(Gl - 1)) == r) {
+          const int li = (int)(jm1 >> lgG);
+          static_for<0, kSW>([&](auto wc) {
+            constexpr int w = decltype(wc)::value;
+            if ((li >> 5) == w) smk[w] ^= 1u << (li & 31);
+          });
+        }
         E += dE;
         if (E < bestE) { bestE = E; bestP = P; }
         h = mix64(h ^ (((uint64_t)(jm1 + 1u) << 32) | (uint64_t)(uint32_t)E));
