@@ -83,19 +83,30 @@ __device__ __forceinline__ uint32_t funnel(uint32_t hi, uint32_t lo, uint32_t sh
   return __builtin_amdgcn_alignbit(hi, lo, sh);
 }
 
-// Min / max over the G consecutive lanes that cooperate on one walk.
+// Min / max over the G consecutive lanes that cooperate on one walk, with DPP
+// lane exchanges inside the VALU (no LDS round trip): quad permutations swap
+// neighbours and pairs within each group of four lanes, and the half-row
+// mirror (lane i <-> 7 - i within eight lanes) joins two quads.
+constexpr int kDppQuadSwap1 = 0xB1;      // quad_perm [1, 0, 3, 2]
+constexpr int kDppQuadSwap2 = 0x4E;      // quad_perm [2, 3, 0, 1]
+constexpr int kDppHalfMirror = 0x141;    // row_half_mirror
+
+template <int CTRL>
+__device__ __forceinline__ uint32_t dpp(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, 0xF, 0xF, false);
+}
 template <int G>
 __device__ __forceinline__ uint32_t group_min(uint32_t v) {
-  if constexpr (G >= 2) v = min(v, (uint32_t)__builtin_amdgcn_ds_swizzle((int)v, 0x041F));
-  if constexpr (G >= 4) v = min(v, (uint32_t)__builtin_amdgcn_ds_swizzle((int)v, 0x081F));
-  if constexpr (G >= 8) v = min(v, (uint32_t)__builtin_amdgcn_ds_swizzle((int)v, 0x101F));
+  if constexpr (G >= 2) v = min(v, dpp<kDppQuadSwap1>(v));
+  if constexpr (G >= 4) v = min(v, dpp<kDppQuadSwap2>(v));
+  if constexpr (G >= 8) v = min(v, dpp<kDppHalfMirror>(v));
   return v;
 }
 template <int G>
 __device__ __forceinline__ uint32_t group_max(uint32_t v) {
-  if constexpr (G >= 2) v = max(v, (uint32_t)__builtin_amdgcn_ds_swizzle((int)v, 0x041F));
-  if constexpr (G >= 4) v = max(v, (uint32_t)__builtin_amdgcn_ds_swizzle((int)v, 0x081F));
-  if constexpr (G >= 8) v = max(v, (uint32_t)__builtin_amdgcn_ds_swizzle((int)v, 0x101F));
+  if constexpr (G >= 2) v = max(v, dpp<kDppQuadSwap1>(v));
+  if constexpr (G >= 4) v = max(v, dpp<kDppQuadSwap2>(v));
+  if constexpr (G >= 8) v = max(v, dpp<kDppHalfMirror>(v));
   return v;
 }
 // Same with the group size known only at run time (G == 0), wave-uniform Gl.
@@ -104,9 +115,9 @@ __device__ __forceinline__ uint32_t grp_min(uint32_t v, int Gl) {
   if constexpr (G > 0) {
     return group_min<G>(v);
   } else {
-    if (Gl >= 2) v = min(v, (uint32_t)__builtin_amdgcn_ds_swizzle((int)v, 0x041F));
-    if (Gl >= 4) v = min(v, (uint32_t)__builtin_amdgcn_ds_swizzle((int)v, 0x081F));
-    if (Gl >= 8) v = min(v, (uint32_t)__builtin_amdgcn_ds_swizzle((int)v, 0x101F));
+    if (Gl >= 2) v = min(v, dpp<kDppQuadSwap1>(v));
+    if (Gl >= 4) v = min(v, dpp<kDppQuadSwap2>(v));
+    if (Gl >= 8) v = min(v, dpp<kDppHalfMirror>(v));
     return v;
   }
 }
@@ -115,9 +126,9 @@ __device__ __forceinline__ uint32_t grp_max(uint32_t v, int Gl) {
   if constexpr (G > 0) {
     return group_max<G>(v);
   } else {
-    if (Gl >= 2) v = max(v, (uint32_t)__builtin_amdgcn_ds_swizzle((int)v, 0x041F));
-    if (Gl >= 4) v = max(v, (uint32_t)__builtin_amdgcn_ds_swizzle((int)v, 0x081F));
-    if (Gl >= 8) v = max(v, (uint32_t)__builtin_amdgcn_ds_swizzle((int)v, 0x101F));
+    if (Gl >= 2) v = max(v, dpp<kDppQuadSwap1>(v));
+    if (Gl >= 4) v = max(v, dpp<kDppQuadSwap2>(v));
+    if (Gl >= 8) v = max(v, dpp<kDppHalfMirror>(v));
     return v;
   }
 }
@@ -842,6 +853,7 @@ __device__ __forceinline__ void run_block(const BlockTask &a, uint8_t *lds) {
     uint32_t pbucket = 0, pslot = 0;
     Key3 pkey{0, 0, 0};
     bool need_scan = false;
+    bool eager = true;            // probe every head in the next round
     bool done = !active;
     uint32_t win = kKeyMax;
 
@@ -935,17 +947,21 @@ __device__ __forceinline__ void run_block(const BlockTask &a, uint8_t *lds) {
           npop = 0;
           hstat = 0;
           pstarted = false;
+          eager = true;
           lane_empty = tk[0] == kKeyMax;
         }
       }
-      // (2) probe the head of every lane whose head status is unknown.
+      // (2) heads.  In a step's first round (and after a lane's rescan) every
+      //     lane probes its head at once; later rounds first merge the heads
+      //     by their known status and probe only the owner of the group's
+      //     best head when that status is still unknown, so a round whose
+      //     best head was probed earlier costs no memory access.
       const uint32_t head = tk[0];
       const bool head_valid = !done && !lane_empty && npop < K && head != kKeyMax;
-      if (head_valid && hstat == 0) {
-        const uint32_t hk = head;
+      auto probe_head = [&]() {
         if (!pstarted) {
-          pkey = flip_key(P, hk & 0xFFu);
-          pbucket = bucket_of_hash(hP ^ zob[hk & 0xFFu], a.n_buckets);
+          pkey = flip_key(P, head & 0xFFu);
+          pbucket = bucket_of_hash(hP ^ zob[head & 0xFFu], a.n_buckets);
           pstarted = true;
         }
         uint32_t slot = 0;
@@ -958,11 +974,16 @@ __device__ __forceinline__ void run_block(const BlockTask &a, uint8_t *lds) {
         } else {
           pbucket = (pbucket + 1u == a.n_buckets) ? 0u : pbucket + 1u;
         }
-      }
+      };
+      if (head_valid && hstat == 0 && eager) probe_head();
+      eager = false;
       // (3) merge the heads of the group.
       const uint32_t my = head_valid ? head : kKeyMax;
       const uint32_t gmin = grp_min<G>(my, Gl);
       const bool owner = head_valid && my == gmin;
+      if (__ballot(owner && hstat == 0) != 0ull) {
+        if (owner && hstat == 0) probe_head();
+      }
       const uint32_t ostat = grp_max<G>(owner ? (uint32_t)(hstat + 1) : 0u, Gl);
       const bool exhausted_any = grp_max<G>((!done && !lane_empty && npop >= K) ? 1u : 0u, Gl) != 0u;
       if (!done) {
