@@ -235,6 +235,20 @@ def run_mixed_batch(steps: int, warmup: int, autotune: bool):
             "distinct_L": len(set(Ls))}
 
 
+def run_solve_target(L: int, target: int, time_limit: float, walks: int, seed: int):
+    """Alg. 1 driver until E <= target (a Table 1 energy) or the time limit:
+    time-to-target and NFEs-to-target against the lambda model's mean 1/lambda."""
+    from paper_2210_15962_amd import labs
+    r = labs.solve(L, walks, target_E=target, time_limit_s=time_limit, seed=seed)
+    D = (L + 1) // 2
+    return {"workload": f"Alg. 1 rounds of {walks} walks x 8D={8 * D} moves at L={L}, target E <= {target}",
+            "seed": seed, "reached": r["reached_target"], "best_E": r["best_E"],
+            "time_to_target_s": r["target_seconds"], "nfes_to_target": r["target_nfes"],
+            "model_mean_nfes": 1.0 / labs.lambda_model(L), "rounds": r["rounds"],
+            "nfes_per_s": r["nfes"] / r["seconds"], "walk_steps_per_s": r["walk_steps"] / r["seconds"],
+            "seconds": r["seconds"]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -253,6 +267,11 @@ def main():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--serve-sweep", type=str, default="",
                     help="comma-separated arrival rates: serve only, one JSON line per rate")
+    ap.add_argument("--solve-target", type=str, default="",
+                    help="L:E -- Alg. 1 driver until E or --solve-time-limit (time-to-target)")
+    ap.add_argument("--solve-time-limit", type=float, default=600.0)
+    ap.add_argument("--solve-walks", type=int, default=262144)
+    ap.add_argument("--solve-seeds", type=str, default="0")
     ap.add_argument("--mixed-batch", action="store_true",
                     help="256-instance mixed-L batch (hipGraph replays) only, default then autotuned")
     args = ap.parse_args()
@@ -264,6 +283,13 @@ def main():
 
     import torch
     from paper_2210_15962_amd import labs
+
+    if args.solve_target:
+        Ls, Es = args.solve_target.split(":")
+        for sd in [int(x) for x in args.solve_seeds.split(",")]:
+            print(json.dumps(run_solve_target(int(Ls), int(Es), args.solve_time_limit, args.solve_walks, sd)),
+                  flush=True)
+        return
 
     if args.mixed_batch:
         for tune in (False, True):

@@ -297,6 +297,74 @@ int32_t labs_serve_wait(labs_server *server, uint64_t req_id, int64_t timeout_ns
                         labs_serve_result *res);
 int32_t labs_serve_stats(labs_server *server, labs_serve_counters *stats);
 
+/*
+ * Solver driver (Alg. 1): rounds of parallel walks from fresh random first
+ * pivots until a stopping condition holds, keeping the global best.  Round r
+ * runs walks_per_round walks of walk_len moves whose starts are walks
+ * r*walks_per_round .. (r+1)*walks_per_round-1 of the labs_starts stream of
+ * `seed`, so a run is reproducible and no start repeats.  After each round
+ * only the per-walk best energies are copied to the host; a sequence is
+ * copied only when it improves the global best.  NFEs grow by
+ * walks_per_round * walk_len * (D - 1) per round, as Alg. 1 counts them.
+ *   walks_per_round : > 0.
+ *   walk_len        : moves per walk; 0 = 8 D (the walk length the paper uses).
+ *   time_limit_s    : stop when the elapsed time reaches it (t_lmt); 0 = none.
+ *   nses_limit      : stop when NFEs reach it (Eq. 6 gives one); 0 = none.
+ *   target_E        : stop as soon as the best energy is <= target_E; 0 = none.
+ *   max_rounds      : 0 = unlimited (then one of the limits above must be set).
+ *   plan            : as for labs_walks (NULL fields = defaults).
+ * Results: best_E, best_seq (W words, packed as labs_walks), rounds run,
+ * NFEs, walk steps made, seconds elapsed, and the time and NFEs at which
+ * target_E was first reached (reached_target = 1), else -1.
+ * workspace: labs_solve_workspace_bytes bytes of device memory.  Blocks the
+ * calling thread (synchronises `stream` every round).
+ * Errors: LABS_EINVAL (bad L or configuration, no stopping condition,
+ * workspace too small), LABS_EDEVICE.
+ */
+typedef struct labs_solve_cfg {
+  int64_t walks_per_round;
+  int64_t walk_len;
+  uint64_t seed;
+  double time_limit_s;
+  double nses_limit;
+  int32_t target_E;
+  int32_t pad;
+  int64_t max_rounds;
+  labs_plan plan;
+} labs_solve_cfg;
+
+typedef struct labs_solve_result {
+  int32_t best_E;
+  int32_t reached_target;
+  uint64_t best_seq[3];
+  int64_t rounds;
+  double nfes;
+  double walk_steps;
+  double seconds;
+  double target_seconds;   /* -1 if the target was not reached */
+  double target_nfes;      /* -1 if the target was not reached */
+} labs_solve_result;
+
+int32_t labs_solve_workspace_bytes(int32_t L, const labs_solve_cfg *cfg, uint64_t *bytes);
+int32_t labs_solve(int32_t L, const labs_solve_cfg *cfg, void *workspace, uint64_t ws_bytes,
+                   void *stream, labs_solve_result *res);
+
+/*
+ * Stopping model of Sec. 4 (host arithmetic).  The solution evaluations one
+ * run needs to reach a known optimum are exponentially distributed with rate
+ * lambda(L) = 0.006753 * 0.8617^L (the trend the paper fits over L = 71..119).
+ *   labs_lambda_model(L)                    : lambda(L).
+ *   labs_nses_limit(L, P, N)                : Eq. 6, NSEs per run so that N
+ *                                             runs reach the optimum with
+ *                                             probability P: ln(1-P)/(-lambda N).
+ *   labs_optimality_probability(L, nses)    : Eq. 7, 1 - exp(-lambda * nses),
+ *                                             nses summed over the runs.
+ * Invalid arguments (L < 1, P outside (0, 1), N < 1, nses < 0) return NaN.
+ */
+double labs_lambda_model(int32_t L);
+double labs_nses_limit(int32_t L, double P, int32_t N);
+double labs_optimality_probability(int32_t L, double nses_total);
+
 #ifdef __cplusplus
 }
 #endif

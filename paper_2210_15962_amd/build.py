@@ -39,7 +39,7 @@ def build(verbose: bool = True) -> str:
     _run([hipcc, "-x", "hip", f"--offload-arch={ARCH}", *COMMON, *DEVICE_FLAGS, *extra, "-c",
           os.path.join(CSRC, "labs_kernels.hip"), "-o", kern_obj])
     objs.append(kern_obj)
-    for host_src in ("labs_api.cpp", "labs_serve.cpp"):
+    for host_src in ("labs_api.cpp", "labs_serve.cpp", "labs_solve.cpp"):
         obj = os.path.join(bdir, host_src.replace(".cpp", ".o"))
         _run([hipcc, *COMMON, "-D__HIP_PLATFORM_AMD__", "-c", os.path.join(CSRC, host_src),
               "-o", obj])

@@ -51,6 +51,19 @@ class Instance(ctypes.Structure):
                 ("out", WalkOut)]
 
 
+class SolveCfg(ctypes.Structure):
+    _fields_ = [("walks_per_round", I64), ("walk_len", I64), ("seed", U64),
+                ("time_limit_s", ctypes.c_double), ("nses_limit", ctypes.c_double),
+                ("target_E", I32), ("pad", I32), ("max_rounds", I64), ("plan", Plan)]
+
+
+class SolveResult(ctypes.Structure):
+    _fields_ = [("best_E", I32), ("reached_target", I32), ("best_seq", U64 * 3), ("rounds", I64),
+                ("nfes", ctypes.c_double), ("walk_steps", ctypes.c_double),
+                ("seconds", ctypes.c_double), ("target_seconds", ctypes.c_double),
+                ("target_nfes", ctypes.c_double)]
+
+
 class ServeCfg(ctypes.Structure):
     _fields_ = [("pool_bytes", U64), ("max_pending", I32), ("lanes_per_walk", I32),
                 ("chunk_steps", I64), ("load_factor", ctypes.c_double)]
@@ -119,6 +132,16 @@ def lib():
         L.labs_autotune.argtypes = [I32, I64, I64, VP, U64, VP, ctypes.POINTER(I32),
                                     ctypes.POINTER(ctypes.c_double)]
         L.labs_autotune.restype = I32
+        L.labs_solve_workspace_bytes.argtypes = [I32, ctypes.POINTER(SolveCfg), ctypes.POINTER(U64)]
+        L.labs_solve_workspace_bytes.restype = I32
+        L.labs_solve.argtypes = [I32, ctypes.POINTER(SolveCfg), VP, U64, VP, ctypes.POINTER(SolveResult)]
+        L.labs_solve.restype = I32
+        L.labs_lambda_model.argtypes = [I32]
+        L.labs_lambda_model.restype = ctypes.c_double
+        L.labs_nses_limit.argtypes = [I32, ctypes.c_double, I32]
+        L.labs_nses_limit.restype = ctypes.c_double
+        L.labs_optimality_probability.argtypes = [I32, ctypes.c_double]
+        L.labs_optimality_probability.restype = ctypes.c_double
         L.labs_serve_create.argtypes = [ctypes.POINTER(ServeCfg), ctypes.POINTER(VP)]
         L.labs_serve_create.restype = I32
         L.labs_serve_destroy.argtypes = [VP]
@@ -456,3 +479,37 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+# ------------------------------------------------------ solver and stopping model
+def solve(L: int, walks_per_round: int, walk_len: int = 0, seed: int = 0, time_limit_s: float = 0.0,
+          nses_limit: float = 0.0, target_E: int = 0, max_rounds: int = 0,
+          plan: Optional[Plan] = None, workspace=None, stream=None, device="cuda") -> dict:
+    """Alg. 1: rounds of walks_per_round fresh walks until a stopping condition
+    holds (labs_solve).  walk_len 0 = 8 D.  Returns the global best and counts."""
+    cfg = SolveCfg(walks_per_round, walk_len, seed & 0xFFFFFFFFFFFFFFFF, time_limit_s, nses_limit,
+                   target_E, 0, max_rounds, plan if plan is not None else Plan(0, 0.0, 0))
+    if workspace is None:
+        nb = U64(0)
+        _check(lib().labs_solve_workspace_bytes(L, ctypes.byref(cfg), ctypes.byref(nb)))
+        workspace = alloc_workspace(nb.value, device=device)
+    res = SolveResult()
+    _check(lib().labs_solve(L, ctypes.byref(cfg), _dptr(workspace), workspace.numel(),
+                            _stream_handle(stream), ctypes.byref(res)))
+    W = key_words(L)
+    return {"best_E": res.best_E, "best_seq": np.array(res.best_seq[:W], dtype=np.uint64),
+            "rounds": res.rounds, "nfes": res.nfes, "walk_steps": res.walk_steps,
+            "seconds": res.seconds, "reached_target": bool(res.reached_target),
+            "target_seconds": res.target_seconds, "target_nfes": res.target_nfes}
+
+
+def lambda_model(L: int) -> float:
+    return lib().labs_lambda_model(L)
+
+
+def nses_limit(L: int, P: float = 0.99, N: int = 100) -> float:
+    return lib().labs_nses_limit(L, P, N)
+
+
+def optimality_probability(L: int, nses_total: float) -> float:
+    return lib().labs_optimality_probability(L, nses_total)

@@ -173,3 +173,35 @@ def test_batch_rejects_cap_counts():
     ws = ctypes.c_void_p(1)
     assert lib.labs_walks_batch(arr, 1, ws, 1 << 30, None) == labs.LABS_EINVAL
     assert b"cap_steps" in lib.labs_last_error()
+
+
+def test_stopping_model_matches_oracle():
+    import math
+    for L in [71, 101, 121, 171, 223, 247]:
+        assert labs.lambda_model(L) == pytest.approx(O.lambda_model(L), rel=1e-14)
+        assert labs.nses_limit(L) == pytest.approx(O.nses_limit(L), rel=1e-14)
+        n = labs.nses_limit(L, 0.99, 100)
+        assert labs.optimality_probability(L, 100 * n) == pytest.approx(0.99, abs=1e-12)
+        assert labs.optimality_probability(L, 1e9) == pytest.approx(O.optimality_probability(L, 1e9), rel=1e-14)
+    for bad in [(0, 0.99, 100), (101, 0.0, 100), (101, 1.0, 100), (101, 0.5, 0)]:
+        assert math.isnan(labs.nses_limit(*bad))
+    assert math.isnan(labs.optimality_probability(101, -1.0))
+    assert math.isnan(labs.lambda_model(0))
+
+
+def test_solve_validation_before_any_launch():
+    lib = labs.lib()
+    nb = labs.U64(0)
+    cfg = labs.SolveCfg(64, 0, 0, 0.0, 0.0, 0, 0, 0, labs.Plan(0, 0.0, 0))
+    assert lib.labs_solve_workspace_bytes(27, ctypes.byref(cfg), ctypes.byref(nb)) == labs.LABS_EINVAL
+    assert b"stopping" in lib.labs_last_error()
+    cfg.max_rounds = 2
+    assert lib.labs_solve_workspace_bytes(28, ctypes.byref(cfg), ctypes.byref(nb)) == labs.LABS_EINVAL
+    assert lib.labs_solve_workspace_bytes(27, ctypes.byref(cfg), ctypes.byref(nb)) == labs.LABS_OK
+    # tables for 64 walks of 8 D = 112 moves, plus per-walk energies, steps and sequences
+    assert nb.value >= labs.workspace_bytes(27, 64, 112) + 64 * (4 + 8 + 8)
+    res = labs.SolveResult()
+    assert lib.labs_solve(27, ctypes.byref(cfg), None, nb.value, None, ctypes.byref(res)) == labs.LABS_EINVAL
+    assert lib.labs_solve(27, ctypes.byref(cfg), ctypes.c_void_p(1), 16, None, ctypes.byref(res)) == labs.LABS_EINVAL
+    cfg.walks_per_round = 0
+    assert lib.labs_solve(27, ctypes.byref(cfg), ctypes.c_void_p(1), 1 << 40, None, ctypes.byref(res)) == labs.LABS_EINVAL
