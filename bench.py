@@ -243,6 +243,7 @@ def run_solve_target(L: int, target: int, time_limit: float, walks: int, seed: i
     D = (L + 1) // 2
     return {"workload": f"Alg. 1 rounds of {walks} walks x 8D={8 * D} moves at L={L}, target E <= {target}",
             "seed": seed, "reached": r["reached_target"], "best_E": r["best_E"],
+            "best_key_hex": "".join("%016x" % int(w) for w in r["best_seq"][::-1]),
             "time_to_target_s": r["target_seconds"], "nfes_to_target": r["target_nfes"],
             "model_mean_nfes": 1.0 / labs.lambda_model(L), "rounds": r["rounds"],
             "nfes_per_s": r["nfes"] / r["seconds"], "walk_steps_per_s": r["walk_steps"] / r["seconds"],
