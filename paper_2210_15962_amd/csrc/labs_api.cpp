@@ -259,10 +259,15 @@ Tuned tuned_for(int32_t L) {
   return Tuned{4, 0.5};
 }
 
+struct BatchGroup {
+  int variant;              // batch kernel (lag-word class) of these items
+  int64_t begin, count;     // their range in the item list
+};
+
 struct BatchPlan {
   std::vector<lsaw::BatchInstanceDev> inst;
   std::vector<lsaw::BatchItemDev> items;
-  int variant;
+  std::vector<BatchGroup> groups;            // one persistent launch each, in order
   uint64_t arena_bytes;
   uint64_t items_off, inst_off, arena_off;   // byte offsets in the workspace
 };
@@ -274,9 +279,9 @@ int32_t plan_batch(const labs_instance *in, int32_t n_inst, BatchPlan &bp) {
   if (n_inst > 0 && !in) return fail(LABS_EINVAL, "NULL instance array");
   bp.inst.clear();
   bp.items.clear();
-  int nw_max = 1;
+  bp.groups.clear();
   bp.arena_bytes = 0;
-  struct Ord { int nw, G, L, idx; };
+  struct Ord { int variant, G, L, idx; };
   std::vector<Ord> order;
   for (int32_t i = 0; i < n_inst; ++i) {
     const labs_instance &x = in[i];
@@ -320,30 +325,54 @@ int32_t plan_batch(const labs_instance *in, int32_t n_inst, BatchPlan &bp) {
     d.resume = 0;
     bp.inst.push_back(d);
     const int nw = lsaw::lag_words_for(x.L);
-    nw_max = std::max(nw_max, nw);
     const int per_block = lsaw::kBlock / lp.lanes_per_walk;
     bp.arena_bytes = std::max(bp.arena_bytes, (uint64_t)per_block * p.table_bytes);
-    order.push_back(Ord{nw, lp.lanes_per_walk, x.L, i});
+    order.push_back(Ord{lsaw::batch_variant(nw), lp.lanes_per_walk, x.L, i});
   }
-  // Longest items first (cost grows with L): the persistent grid then ends
-  // on short items, which keeps the tail of the launch short.
+  // Classes whose kernels reach the same occupancy share one launch on the
+  // largest class's kernel (a shorter length runs on a longer class's kernel
+  // exactly): separate launches would only add tails.
+  {
+    int present[8] = {0};
+    for (const Ord &o : order) present[o.variant] = 1;
+    int merged[8] = {0, 0, 2, 3, 4, 5, 6, 6};
+    int top = 0, top_occ = 0;
+    for (int v = 6; v >= 2; --v) {
+      if (!present[v]) continue;
+      int occ = 0;
+      if (lsaw::batch_blocks_per_cu(v, &occ) != hipSuccess) occ = 0;
+      if (top && occ <= top_occ) {
+        merged[v] = top;
+      } else {
+        top = v;
+        top_occ = occ;
+      }
+    }
+    for (Ord &o : order) o.variant = merged[o.variant];
+  }
+  // One launch per lag-word class (each at its own occupancy), largest class
+  // first; inside a class the longest items first (cost grows with L), so a
+  // persistent grid ends on short items and its tail stays short.
   std::stable_sort(order.begin(), order.end(), [](const Ord &a, const Ord &b) {
+    if (a.variant != b.variant) return a.variant > b.variant;
     if (a.L != b.L) return a.L > b.L;
     return a.G < b.G;
   });
   for (const Ord &o : order) {
     const int per_block = lsaw::kBlock / o.G;
     const int64_t n = in[o.idx].n_walks;
+    if (n > 0 && (bp.groups.empty() || bp.groups.back().variant != o.variant))
+      bp.groups.push_back(BatchGroup{o.variant, (int64_t)bp.items.size(), 0});
     for (int64_t b = 0; b < n; b += per_block) {
       lsaw::BatchItemDev it{};
       it.inst = o.idx;
-      it.code = (o.nw << 4) | o.G;
+      it.code = (lsaw::lag_words_for(in[o.idx].L) << 4) | o.G;
       it.n_walks = (int32_t)std::min<int64_t>(per_block, n - b);
       it.walk_begin = b;
       bp.items.push_back(it);
+      bp.groups.back().count++;
     }
   }
-  bp.variant = lsaw::batch_variant(nw_max);
   bp.items_off = 256;
   bp.inst_off = align256(bp.items_off + bp.items.size() * sizeof(lsaw::BatchItemDev));
   bp.arena_off = align256(bp.inst_off + bp.inst.size() * sizeof(lsaw::BatchInstanceDev));
@@ -360,24 +389,26 @@ int32_t device_resident_blocks(int variant, int64_t *blocks) {
   return LABS_OK;
 }
 
-int32_t batch_grid(const BatchPlan &bp, uint64_t ws_bytes, int *grid) {
+// Persistent grid of one group: resident workgroups of its kernel, at most one
+// per item, and no more than the workspace has arena slices for.
+int32_t batch_grid(const BatchPlan &bp, const BatchGroup &grp, uint64_t ws_bytes, int *grid) {
   int64_t resident = 0;
-  int32_t rc = device_resident_blocks(bp.variant, &resident);
+  int32_t rc = device_resident_blocks(grp.variant, &resident);
   if (rc != LABS_OK) return rc;
   if (ws_bytes < bp.arena_off + bp.arena_bytes)
     return fail(LABS_EINVAL, "workspace of %llu bytes is below the minimum %llu",
                 (unsigned long long)ws_bytes, (unsigned long long)(bp.arena_off + bp.arena_bytes));
   const uint64_t fit = (ws_bytes - bp.arena_off) / std::max<uint64_t>(bp.arena_bytes, 1);
-  int64_t g = std::min<int64_t>((int64_t)bp.items.size(), resident);
+  int64_t g = std::min<int64_t>(grp.count, resident);
   g = std::min<int64_t>(g, (int64_t)fit);
   *grid = (int)g;
   return LABS_OK;
 }
 
-lsaw::BatchLaunch batch_launch(const BatchPlan &bp, uint8_t *ws) {
+lsaw::BatchLaunch batch_launch(const BatchPlan &bp, uint8_t *ws, const BatchGroup &grp) {
   lsaw::BatchLaunch b;
-  b.items = reinterpret_cast<const lsaw::BatchItemDev *>(ws + bp.items_off);
-  b.n_items = (int64_t)bp.items.size();
+  b.items = reinterpret_cast<const lsaw::BatchItemDev *>(ws + bp.items_off) + grp.begin;
+  b.n_items = grp.count;
   b.inst = reinterpret_cast<const lsaw::BatchInstanceDev *>(ws + bp.inst_off);
   b.counter = reinterpret_cast<uint32_t *>(ws);
   b.arena = ws + bp.arena_off;
@@ -399,11 +430,14 @@ int32_t labs_batch_workspace_bytes(const labs_instance *inst, int32_t n_inst, ui
   BatchPlan bp;
   int32_t rc = plan_batch(inst, n_inst, bp);
   if (rc != LABS_OK) return rc;
-  int64_t resident = 0;
-  rc = device_resident_blocks(bp.variant, &resident);
-  if (rc != LABS_OK) return rc;
-  const int64_t g = std::min<int64_t>((int64_t)bp.items.size(), resident);
-  *bytes = bp.arena_off + (uint64_t)std::max<int64_t>(g, 1) * bp.arena_bytes;
+  int64_t g = 1;
+  for (const BatchGroup &grp : bp.groups) {
+    int64_t resident = 0;
+    rc = device_resident_blocks(grp.variant, &resident);
+    if (rc != LABS_OK) return rc;
+    g = std::max<int64_t>(g, std::min<int64_t>(grp.count, resident));
+  }
+  *bytes = bp.arena_off + (uint64_t)g * bp.arena_bytes;
   return ok();
 }
 
@@ -414,9 +448,13 @@ int32_t labs_walks_batch(const labs_instance *inst, int32_t n_inst, void *worksp
   if (rc != LABS_OK) return rc;
   if (bp.items.empty()) return ok();
   if (!workspace) return fail(LABS_EINVAL, "NULL workspace");
-  int grid = 0;
-  rc = batch_grid(bp, ws_bytes, &grid);
-  if (rc != LABS_OK) return rc;
+  std::vector<int> grids;
+  for (const BatchGroup &grp : bp.groups) {
+    int grid = 0;
+    rc = batch_grid(bp, grp, ws_bytes, &grid);
+    if (rc != LABS_OK) return rc;
+    grids.push_back(grid);
+  }
   uint8_t *ws = static_cast<uint8_t *>(workspace);
   hipStream_t st = as_stream(stream);
   hipError_t e = hipMemcpyAsync(ws + bp.items_off, bp.items.data(),
@@ -425,8 +463,11 @@ int32_t labs_walks_batch(const labs_instance *inst, int32_t n_inst, void *worksp
     e = hipMemcpyAsync(ws + bp.inst_off, bp.inst.data(), bp.inst.size() * sizeof(lsaw::BatchInstanceDev),
                        hipMemcpyHostToDevice, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);   // host vectors die on return
-  if (e == hipSuccess) e = lsaw::launch_batch_reset(reinterpret_cast<uint32_t *>(ws), st);
-  if (e == hipSuccess) e = lsaw::launch_batch(batch_launch(bp, ws), bp.variant, grid, st);
+  for (size_t k = 0; k < bp.groups.size() && e == hipSuccess; ++k) {
+    e = lsaw::launch_batch_reset(reinterpret_cast<uint32_t *>(ws), st);
+    if (e == hipSuccess)
+      e = lsaw::launch_batch(batch_launch(bp, ws, bp.groups[k]), bp.groups[k].variant, grids[k], st);
+  }
   if (e != hipSuccess) return fail(LABS_EDEVICE, "batch launch: %s", hipGetErrorString(e));
   return ok();
 }
@@ -439,10 +480,12 @@ int32_t labs_batch_graph_create(const labs_instance *inst, int32_t n_inst, void 
   int32_t rc = plan_batch(inst, n_inst, bp);
   if (rc != LABS_OK) return rc;
   if (!workspace) return fail(LABS_EINVAL, "NULL workspace");
-  int grid = 0;
-  if (!bp.items.empty()) {
-    rc = batch_grid(bp, ws_bytes, &grid);
+  std::vector<int> grids;
+  for (const BatchGroup &grp : bp.groups) {
+    int grid = 0;
+    rc = batch_grid(bp, grp, ws_bytes, &grid);
     if (rc != LABS_OK) return rc;
+    grids.push_back(grid);
   }
   uint8_t *ws = static_cast<uint8_t *>(workspace);
   hipError_t e = hipSuccess;
@@ -458,8 +501,13 @@ int32_t labs_batch_graph_create(const labs_instance *inst, int32_t n_inst, void 
   labs_batch_graph *g = new labs_batch_graph{nullptr, nullptr};
   if (e == hipSuccess) e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
   if (e == hipSuccess) {
+    // a reset kernel (not a memset node) before every group's launch
     hipError_t k = lsaw::launch_batch_reset(reinterpret_cast<uint32_t *>(ws), cs);
-    if (k == hipSuccess && !bp.items.empty()) k = lsaw::launch_batch(batch_launch(bp, ws), bp.variant, grid, cs);
+    for (size_t q = 0; q < bp.groups.size() && k == hipSuccess; ++q) {
+      if (q > 0) k = lsaw::launch_batch_reset(reinterpret_cast<uint32_t *>(ws), cs);
+      if (k == hipSuccess)
+        k = lsaw::launch_batch(batch_launch(bp, ws, bp.groups[q]), bp.groups[q].variant, grids[q], cs);
+    }
     e = hipStreamEndCapture(cs, &g->graph);
     if (e == hipSuccess) e = k;
   }

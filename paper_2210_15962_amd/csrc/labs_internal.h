@@ -112,8 +112,8 @@ hipError_t launch_starts(int32_t L, int64_t n_walks, uint64_t seed, uint64_t *ou
 hipError_t launch_walks(const WalkLaunch &w, hipStream_t stream);
 // Dynamic LDS bytes the walk kernel needs for length L (0 if unsupported).
 size_t walk_lds_bytes(int32_t L);
-// Batch kernel variant able to run lag-word classes up to nw_max (2, 4 or 6).
-int batch_variant(int nw_max);
+// Batch kernel of lag-word class nw (2..6; class 1 runs on the class-2 kernel).
+int batch_variant(int nw);
 size_t batch_lds_bytes(int variant);
 hipError_t batch_blocks_per_cu(int variant, int *blocks);
 hipError_t launch_batch_reset(uint32_t *counter, hipStream_t stream);

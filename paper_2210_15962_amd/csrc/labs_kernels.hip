@@ -462,6 +462,9 @@ __host__ __device__ constexpr uint64_t words_mask(int nw, int G, bool exact_clas
 
 template <int NW, int G>
 struct WordsMask {
+  // walk kernels: lengths of exactly class NW; batch kernels: every class up
+  // to NW (classes of equal occupancy share the largest one's kernel), any of
+  // 2, 4 or 8 lanes per walk
   static constexpr uint64_t value =
       G > 0 ? words_mask(NW, G, true)
             : (words_mask(NW, 2, false) | words_mask(NW, 4, false) | words_mask(NW, 8, false));
@@ -1312,12 +1315,16 @@ hipError_t launch_walks(const WalkLaunch &w, hipStream_t stream) {
 }
 
 
-int batch_variant(int nw_max) { return nw_max <= 2 ? 2 : (nw_max <= 4 ? 4 : 6); }
+// One batch kernel per lag-word class (NW 1 and 2 share the first), so that
+// each class runs at the occupancy of its own register footprint.
+int batch_variant(int nw) { return nw <= 2 ? 2 : (nw > 6 ? 6 : nw); }
 
 size_t batch_lds_bytes(int variant) {
   switch (variant) {
     case 2: return lds_for<2>();
+    case 3: return lds_for<3>();
     case 4: return lds_for<4>();
+    case 5: return lds_for<5>();
     default: return lds_for<6>();
   }
 }
@@ -1328,7 +1335,9 @@ static const void *batch_fn() { return reinterpret_cast<const void *>(batch_kern
 static const void *batch_kernel_ptr(int variant) {
   switch (variant) {
     case 2: return batch_fn<2>();
+    case 3: return batch_fn<3>();
     case 4: return batch_fn<4>();
+    case 5: return batch_fn<5>();
     default: return batch_fn<6>();
   }
 }
@@ -1360,7 +1369,9 @@ hipError_t launch_batch(const BatchLaunch &b, int variant, int grid, hipStream_t
   if (grid <= 0) return hipSuccess;
   switch (variant) {
     case 2: return launch_batch_v<2>(b, grid, stream);
+    case 3: return launch_batch_v<3>(b, grid, stream);
     case 4: return launch_batch_v<4>(b, grid, stream);
+    case 5: return launch_batch_v<5>(b, grid, stream);
     default: return launch_batch_v<6>(b, grid, stream);
   }
 }

@@ -111,6 +111,9 @@ struct Request {
 };
 
 constexpr int kMaxItems = 1 << 17;
+// Control region: queue heads (one per kernel class, 64 bytes apart), then
+// the work list and the instance table of the current launch.
+constexpr uint64_t kCtlHead = 512;
 constexpr int kMaxInst = 8192;
 
 }  // namespace
@@ -118,6 +121,7 @@ constexpr int kMaxInst = 8192;
 struct labs_server {
   int device = 0;
   hipStream_t stream = nullptr;
+  hipStream_t group_stream[8] = {nullptr};  // one per kernel class (2..6), default priority
   uint8_t *pool = nullptr;          // control region, then request ranges
   uint64_t pool_bytes = 0;
   uint64_t ctl_bytes = 0;           // control region size
@@ -210,25 +214,49 @@ void run_worker(labs_server *s) {
     inst.clear();
     items.clear();
     budget.clear();
-    int nw_max = 1;
-    for (Request *q : run) nw_max = std::max(nw_max, lsaw::lag_words_for(q->L));
-    const int variant = lsaw::batch_variant(nw_max);
-    int per_cu = 1, cus = 256;
-    (void)lsaw::batch_blocks_per_cu(variant, &per_cu);
+    // One persistent launch per lag-word class present (each at the
+    // occupancy of its own kernel), largest class first.
+    int cus = 256;
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, s->device);
-    const int64_t slots = (int64_t)std::max(per_cu, 1) * cus;
-    // Lanes per walk for this launch (walk state and tables do not depend on
-    // it): a request's own choice if it has one, else 4 or 8, whichever
-    // fills the resident workgroups in whole rounds better (8 lanes cost
-    // about 20% more per walk step than 4: the per-move work is shared by
-    // half as many candidates per lane).
-    int64_t items4 = 0;
-    for (Request *q : run) items4 += items_of(*q, 4);
-    auto fill = [&](int64_t n) {
-      const int64_t rounds = (n + slots - 1) / slots;
-      return rounds > 0 ? (double)n / (double)(rounds * slots) : 0.0;
-    };
-    const int auto_lanes = 0.8 * fill(2 * items4) > fill(items4) ? 8 : 4;
+    // Classes whose kernels reach the same occupancy share one launch on the
+    // largest class's kernel (separate launches would only add tails).
+    int launch_v[8] = {0, 0, 2, 3, 4, 5, 6, 6};
+    {
+      int present[8] = {0};
+      for (Request *q : run) present[lsaw::batch_variant(lsaw::lag_words_for(q->L))] = 1;
+      int top = 0, top_occ = 0;
+      for (int v = 6; v >= 2; --v) {
+        if (!present[v]) continue;
+        int occ = 0;
+        if (lsaw::batch_blocks_per_cu(v, &occ) != hipSuccess) occ = 0;
+        if (top && occ <= top_occ) {
+          launch_v[v] = top;
+        } else {
+          top = v;
+          top_occ = occ;
+        }
+      }
+    }
+    auto class_launch = [&](int L) { return launch_v[lsaw::batch_variant(lsaw::lag_words_for(L))]; };
+    int64_t slots_v[8] = {0}, items4_v[8] = {0};
+    int lanes_v[8] = {4, 4, 4, 4, 4, 4, 4, 4};
+    for (Request *q : run) items4_v[class_launch(q->L)] += items_of(*q, 4);
+    for (int v = 2; v <= 6; ++v) {
+      if (!items4_v[v]) continue;
+      int per_cu = 1;
+      (void)lsaw::batch_blocks_per_cu(v, &per_cu);
+      slots_v[v] = (int64_t)std::max(per_cu, 1) * cus;
+      // Lanes per walk for this launch (walk state and tables do not depend
+      // on it): a request's own choice if it has one, else 4 or 8, whichever
+      // fills the class's resident workgroups in whole rounds better (8 lanes
+      // cost about 20% more per walk step than 4: the per-move work is shared
+      // by half as many candidates per lane).
+      auto fill = [&](int64_t n) {
+        const int64_t rounds = (n + slots_v[v] - 1) / slots_v[v];
+        return rounds > 0 ? (double)n / (double)(rounds * slots_v[v]) : 0.0;
+      };
+      lanes_v[v] = 0.8 * fill(2 * items4_v[v]) > fill(items4_v[v]) ? 8 : 4;
+    }
     for (size_t k = 0; k < run.size(); ++k) {
       Request *q = run[k];
       uint8_t *b = s->pool + s->ctl_bytes + q->off;
@@ -259,7 +287,7 @@ void run_worker(labs_server *s) {
       d.step_end = q->progress + take;
       d.resume = q->launched ? 1 : 0;
       inst.push_back(d);
-      const int lanes = q->lanes ? q->lanes : auto_lanes;
+      const int lanes = q->lanes ? q->lanes : lanes_v[class_launch(q->L)];
       const int per = lsaw::kBlock / lanes;
       for (int64_t w = 0; w < q->n_walks; w += per) {
         lsaw::BatchItemDev it{};
@@ -270,13 +298,16 @@ void run_worker(labs_server *s) {
         items.push_back(it);
       }
     }
-    // longest items first (cost grows with L) keeps the launch's tail short
+    // by class, then longest items first (cost grows with L) so that each
+    // persistent grid ends on short items
+    auto variant_of = [&](const lsaw::BatchItemDev &x) { return class_launch(inst[x.inst].L); };
     std::stable_sort(items.begin(), items.end(), [&](const lsaw::BatchItemDev &x, const lsaw::BatchItemDev &y) {
+      const int vx = variant_of(x), vy = variant_of(y);
+      if (vx != vy) return vx > vy;
       return inst[x.inst].L > inst[y.inst].L;
     });
-    const int grid = (int)std::min<int64_t>((int64_t)items.size(), slots);
     uint8_t *ctl = s->pool;
-    const uint64_t items_off = 256;
+    const uint64_t items_off = kCtlHead;
     const uint64_t inst_off = al(items_off + (uint64_t)kMaxItems * sizeof(lsaw::BatchItemDev));
     lsaw::BatchLaunch bl;
     bl.items = reinterpret_cast<const lsaw::BatchItemDev *>(ctl + items_off);
@@ -291,9 +322,26 @@ void run_worker(labs_server *s) {
     if (e == hipSuccess)
       e = hipMemcpyAsync(ctl + inst_off, inst.data(), inst.size() * sizeof(lsaw::BatchInstanceDev),
                          hipMemcpyHostToDevice, s->stream);
-    if (e == hipSuccess) e = lsaw::launch_batch_reset(bl.counter, s->stream);
-    if (e == hipSuccess) e = lsaw::launch_batch(bl, variant, grid, s->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);   // work lists in place
+    for (size_t g0 = 0; g0 < items.size() && e == hipSuccess;) {
+      const int v = variant_of(items[g0]);
+      size_t g1 = g0;
+      while (g1 < items.size() && variant_of(items[g1]) == v) ++g1;
+      lsaw::BatchLaunch bg = bl;
+      bg.items = bl.items + g0;
+      bg.n_items = (int64_t)(g1 - g0);
+      const int grid = (int)std::min<int64_t>(bg.n_items, slots_v[v]);
+      // Groups hold disjoint requests, so they run concurrently, each on its
+      // own stream with its own queue head: one group's tail overlaps the
+      // other's work.  Every workgroup only drains its own queue, so the
+      // grids finish whatever share of the GPU each gets.
+      bg.counter = reinterpret_cast<uint32_t *>(ctl) + 16 * v;
+      e = lsaw::launch_batch_reset(bg.counter, s->group_stream[v]);
+      if (e == hipSuccess) e = lsaw::launch_batch(bg, v, grid, s->group_stream[v]);
+      g0 = g1;
+    }
+    for (int v = 2; v <= 6; ++v)
+      if (e == hipSuccess) e = hipStreamSynchronize(s->group_stream[v]);
     const int64_t t1 = now_ns();
     std::vector<Request *> done;
     for (size_t k = 0; k < run.size() && e == hipSuccess; ++k) {
@@ -374,14 +422,19 @@ int32_t labs_serve_create(const labs_serve_cfg *cfg, labs_server **server) {
   hipError_t e = hipGetDevice(&s->device);
   size_t free_b = 0, total_b = 0;
   if (e == hipSuccess) e = hipMemGetInfo(&free_b, &total_b);
-  s->ctl_bytes = al(256 + (uint64_t)kMaxItems * sizeof(lsaw::BatchItemDev)) +
+  s->ctl_bytes = al(kCtlHead + (uint64_t)kMaxItems * sizeof(lsaw::BatchItemDev)) +
                  al((uint64_t)kMaxInst * sizeof(lsaw::BatchInstanceDev));
   uint64_t want = c.pool_bytes ? c.pool_bytes : (uint64_t)(free_b / 2);
   want = al(want);
   if (e == hipSuccess && want <= s->ctl_bytes) e = hipErrorInvalidValue;
   if (e == hipSuccess) e = hipMalloc(&s->pool, want);
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking);
+  for (int v = 2; v <= 6 && e == hipSuccess; ++v)
+    e = hipStreamCreateWithFlags(&s->group_stream[v], hipStreamNonBlocking);
   if (e != hipSuccess) {
+    if (s->stream) (void)hipStreamDestroy(s->stream);
+    for (int v = 2; v <= 6; ++v)
+      if (s->group_stream[v]) (void)hipStreamDestroy(s->group_stream[v]);
     if (s->pool) (void)hipFree(s->pool);
     delete s;
     return lsaw::set_error(e == hipErrorOutOfMemory ? LABS_ENOMEM : LABS_EDEVICE, "serve create: %s",
@@ -405,6 +458,8 @@ int32_t labs_serve_destroy(labs_server *s) {
   if (s->worker.joinable()) s->worker.join();
   for (auto &kv : s->all) delete kv.second;
   if (s->stream) (void)hipStreamDestroy(s->stream);
+  for (int v = 2; v <= 6; ++v)
+    if (s->group_stream[v]) (void)hipStreamDestroy(s->group_stream[v]);
   if (s->pool) (void)hipFree(s->pool);
   delete s;
   return lsaw::clear_error();
