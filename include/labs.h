@@ -181,16 +181,20 @@ typedef struct labs_instance {
 
 /*
  * labs_batch_workspace_bytes -- workspace for labs_walks_batch /
- * labs_batch_graph_create: queue control, the work-item list and one visited-
- * table arena per resident workgroup of the current device (queries the
- * device; LABS_EDEVICE without one).  Smaller workspaces run with fewer
- * resident workgroups.
+ * labs_batch_graph_create: queue heads, the work-item list and one visited-
+ * table arena slice per resident workgroup of the current device (queries the
+ * device; LABS_EDEVICE without one).  A batch runs as one persistent launch
+ * per group of lag-word classes of equal occupancy; with this size the groups
+ * run one after another.  A workspace with a slice for every resident
+ * workgroup of every group at once lets the groups run concurrently (on
+ * library-owned side streams forked from and joined back to `stream`);
+ * smaller workspaces run with fewer resident workgroups.
  */
 int32_t labs_batch_workspace_bytes(const labs_instance *inst, int32_t n_inst, uint64_t *bytes);
 
 /*
- * labs_walks_batch -- run every instance (host array inst[0..n_inst-1]) in one
- * persistent launch on `stream`.  The work-item list is uploaded into the
+ * labs_walks_batch -- run every instance (host array inst[0..n_inst-1]) in
+ * persistent launches (one per class group, see above) on `stream`.  The work-item list is uploaded into the
  * workspace with an asynchronous copy from host memory.  Errors: LABS_EINVAL
  * (any invalid instance, workspace below one arena), LABS_EDEVICE.
  */

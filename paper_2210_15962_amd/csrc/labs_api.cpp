@@ -259,6 +259,9 @@ Tuned tuned_for(int32_t L) {
   return Tuned{4, 0.5};
 }
 
+constexpr int kMaxGroups = 8;          // more than the kernel classes (2..6)
+constexpr uint64_t kQueueHeads = 512;  // queue heads at 64-byte spacing, then the work list
+
 struct BatchGroup {
   int variant;              // batch kernel (lag-word class) of these items
   int64_t begin, count;     // their range in the item list
@@ -373,7 +376,7 @@ int32_t plan_batch(const labs_instance *in, int32_t n_inst, BatchPlan &bp) {
       bp.groups.back().count++;
     }
   }
-  bp.items_off = 256;
+  bp.items_off = kQueueHeads;
   bp.inst_off = align256(bp.items_off + bp.items.size() * sizeof(lsaw::BatchItemDev));
   bp.arena_off = align256(bp.inst_off + bp.inst.size() * sizeof(lsaw::BatchInstanceDev));
   return LABS_OK;
@@ -389,31 +392,104 @@ int32_t device_resident_blocks(int variant, int64_t *blocks) {
   return LABS_OK;
 }
 
-// Persistent grid of one group: resident workgroups of its kernel, at most one
-// per item, and no more than the workspace has arena slices for.
-int32_t batch_grid(const BatchPlan &bp, const BatchGroup &grp, uint64_t ws_bytes, int *grid) {
-  int64_t resident = 0;
-  int32_t rc = device_resident_blocks(grp.variant, &resident);
-  if (rc != LABS_OK) return rc;
+// Persistent grids of the groups: resident workgroups of each kernel, at most
+// one per item.  The groups run concurrently when the workspace holds a slice
+// for every workgroup of every group, else one after another with each grid
+// cut to the slices there are.
+int32_t batch_grids(const BatchPlan &bp, uint64_t ws_bytes, std::vector<int> &grids, bool *concurrent) {
+  grids.clear();
   if (ws_bytes < bp.arena_off + bp.arena_bytes)
     return fail(LABS_EINVAL, "workspace of %llu bytes is below the minimum %llu",
                 (unsigned long long)ws_bytes, (unsigned long long)(bp.arena_off + bp.arena_bytes));
   const uint64_t fit = (ws_bytes - bp.arena_off) / std::max<uint64_t>(bp.arena_bytes, 1);
-  int64_t g = std::min<int64_t>(grp.count, resident);
-  g = std::min<int64_t>(g, (int64_t)fit);
-  *grid = (int)g;
+  uint64_t total = 0;
+  for (const BatchGroup &grp : bp.groups) {
+    int64_t resident = 0;
+    int32_t rc = device_resident_blocks(grp.variant, &resident);
+    if (rc != LABS_OK) return rc;
+    grids.push_back((int)std::min<int64_t>(grp.count, resident));
+    total += (uint64_t)grids.back();
+  }
+  *concurrent = total <= fit;
+  if (!*concurrent)
+    for (int &g : grids) g = (int)std::min<uint64_t>((uint64_t)g, fit);
   return LABS_OK;
 }
 
-lsaw::BatchLaunch batch_launch(const BatchPlan &bp, uint8_t *ws, const BatchGroup &grp) {
+lsaw::BatchLaunch batch_launch(const BatchPlan &bp, uint8_t *ws, size_t k) {
+  const BatchGroup &grp = bp.groups[k];
   lsaw::BatchLaunch b;
   b.items = reinterpret_cast<const lsaw::BatchItemDev *>(ws + bp.items_off) + grp.begin;
   b.n_items = grp.count;
   b.inst = reinterpret_cast<const lsaw::BatchInstanceDev *>(ws + bp.inst_off);
-  b.counter = reinterpret_cast<uint32_t *>(ws);
+  b.counter = reinterpret_cast<uint32_t *>(ws + 64 * k);      // own queue head per group
   b.arena = ws + bp.arena_off;
   b.arena_bytes = bp.arena_bytes;
   return b;
+}
+
+// Library-owned side streams (default priority) and fork/join events of one
+// device, created on first use.  Group 0 of a batch runs on the caller's
+// stream and group k on side stream k; the groups hold disjoint instances,
+// their own queue heads and disjoint ranges of arena slices.
+struct SideStreams {
+  hipStream_t s[kMaxGroups] = {nullptr};
+  hipEvent_t fork = nullptr, join[kMaxGroups] = {nullptr};
+};
+std::mutex g_side_mu;                 // held from fork to join of one enqueue
+std::map<int, SideStreams> g_side;
+
+hipError_t side_streams(SideStreams **out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  SideStreams &ss = g_side[dev];
+  if (!ss.fork) {
+    for (int k = 1; k < kMaxGroups && e == hipSuccess; ++k) {
+      e = hipStreamCreateWithFlags(&ss.s[k], hipStreamNonBlocking);
+      if (e == hipSuccess) e = hipEventCreateWithFlags(&ss.join[k], hipEventDisableTiming);
+    }
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&ss.fork, hipEventDisableTiming);
+    if (e != hipSuccess) return e;
+  }
+  *out = &ss;
+  return hipSuccess;
+}
+
+// Enqueue every group of a batch on `st`.  Concurrent: group 0 on st itself,
+// the others forked onto side streams and joined back, each on its own range
+// of arena slices (one group's tail overlaps another's work).  Otherwise the
+// groups run one after another on st, all from slice 0.  Works under stream
+// capture.
+hipError_t enqueue_groups(const BatchPlan &bp, uint8_t *ws, const std::vector<int> &grids,
+                          bool concurrent, hipStream_t st) {
+  if (bp.groups.empty()) return hipSuccess;
+  if (bp.groups.size() == 1 || !concurrent) {
+    hipError_t e = hipSuccess;
+    for (size_t k = 0; k < bp.groups.size() && e == hipSuccess; ++k) {
+      lsaw::BatchLaunch b = batch_launch(bp, ws, k);
+      e = lsaw::launch_batch_reset(b.counter, st);
+      if (e == hipSuccess) e = lsaw::launch_batch(b, bp.groups[k].variant, grids[k], st);
+    }
+    return e;
+  }
+  std::lock_guard<std::mutex> lk(g_side_mu);
+  SideStreams *ss = nullptr;
+  hipError_t e = side_streams(&ss);
+  if (e == hipSuccess) e = hipEventRecord(ss->fork, st);
+  uint64_t first = 0;
+  for (size_t k = 0; k < bp.groups.size() && e == hipSuccess; ++k) {
+    hipStream_t gs = k == 0 ? st : ss->s[k];
+    if (k > 0) e = hipStreamWaitEvent(gs, ss->fork, 0);
+    lsaw::BatchLaunch b = batch_launch(bp, ws, k);
+    b.arena += first * bp.arena_bytes;            // disjoint arena slices per group
+    first += (uint64_t)grids[k];
+    if (e == hipSuccess) e = lsaw::launch_batch_reset(b.counter, gs);
+    if (e == hipSuccess) e = lsaw::launch_batch(b, bp.groups[k].variant, grids[k], gs);
+    if (e == hipSuccess && k > 0) e = hipEventRecord(ss->join[k], gs);
+  }
+  for (size_t k = 1; k < bp.groups.size() && e == hipSuccess; ++k) e = hipStreamWaitEvent(st, ss->join[k], 0);
+  return e;
 }
 
 }  // namespace
@@ -430,6 +506,9 @@ int32_t labs_batch_workspace_bytes(const labs_instance *inst, int32_t n_inst, ui
   BatchPlan bp;
   int32_t rc = plan_batch(inst, n_inst, bp);
   if (rc != LABS_OK) return rc;
+  // Groups one after another: the largest group's grid of arena slices.
+  // (A workspace with a slice for every workgroup of every group lets the
+  // groups run concurrently; see labs_batch_workspace_bytes in labs.h.)
   int64_t g = 1;
   for (const BatchGroup &grp : bp.groups) {
     int64_t resident = 0;
@@ -449,12 +528,9 @@ int32_t labs_walks_batch(const labs_instance *inst, int32_t n_inst, void *worksp
   if (bp.items.empty()) return ok();
   if (!workspace) return fail(LABS_EINVAL, "NULL workspace");
   std::vector<int> grids;
-  for (const BatchGroup &grp : bp.groups) {
-    int grid = 0;
-    rc = batch_grid(bp, grp, ws_bytes, &grid);
-    if (rc != LABS_OK) return rc;
-    grids.push_back(grid);
-  }
+  bool concurrent = false;
+  rc = batch_grids(bp, ws_bytes, grids, &concurrent);
+  if (rc != LABS_OK) return rc;
   uint8_t *ws = static_cast<uint8_t *>(workspace);
   hipStream_t st = as_stream(stream);
   hipError_t e = hipMemcpyAsync(ws + bp.items_off, bp.items.data(),
@@ -463,11 +539,7 @@ int32_t labs_walks_batch(const labs_instance *inst, int32_t n_inst, void *worksp
     e = hipMemcpyAsync(ws + bp.inst_off, bp.inst.data(), bp.inst.size() * sizeof(lsaw::BatchInstanceDev),
                        hipMemcpyHostToDevice, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);   // host vectors die on return
-  for (size_t k = 0; k < bp.groups.size() && e == hipSuccess; ++k) {
-    e = lsaw::launch_batch_reset(reinterpret_cast<uint32_t *>(ws), st);
-    if (e == hipSuccess)
-      e = lsaw::launch_batch(batch_launch(bp, ws, bp.groups[k]), bp.groups[k].variant, grids[k], st);
-  }
+  if (e == hipSuccess) e = enqueue_groups(bp, ws, grids, concurrent, st);
   if (e != hipSuccess) return fail(LABS_EDEVICE, "batch launch: %s", hipGetErrorString(e));
   return ok();
 }
@@ -481,11 +553,10 @@ int32_t labs_batch_graph_create(const labs_instance *inst, int32_t n_inst, void 
   if (rc != LABS_OK) return rc;
   if (!workspace) return fail(LABS_EINVAL, "NULL workspace");
   std::vector<int> grids;
-  for (const BatchGroup &grp : bp.groups) {
-    int grid = 0;
-    rc = batch_grid(bp, grp, ws_bytes, &grid);
+  bool concurrent = false;
+  if (!bp.groups.empty()) {
+    rc = batch_grids(bp, ws_bytes, grids, &concurrent);
     if (rc != LABS_OK) return rc;
-    grids.push_back(grid);
   }
   uint8_t *ws = static_cast<uint8_t *>(workspace);
   hipError_t e = hipSuccess;
@@ -502,12 +573,7 @@ int32_t labs_batch_graph_create(const labs_instance *inst, int32_t n_inst, void 
   if (e == hipSuccess) e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
   if (e == hipSuccess) {
     // a reset kernel (not a memset node) before every group's launch
-    hipError_t k = lsaw::launch_batch_reset(reinterpret_cast<uint32_t *>(ws), cs);
-    for (size_t q = 0; q < bp.groups.size() && k == hipSuccess; ++q) {
-      if (q > 0) k = lsaw::launch_batch_reset(reinterpret_cast<uint32_t *>(ws), cs);
-      if (k == hipSuccess)
-        k = lsaw::launch_batch(batch_launch(bp, ws, bp.groups[q]), bp.groups[q].variant, grids[q], cs);
-    }
+    hipError_t k = enqueue_groups(bp, ws, grids, concurrent, cs);
     e = hipStreamEndCapture(cs, &g->graph);
     if (e == hipSuccess) e = k;
   }

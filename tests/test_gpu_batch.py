@@ -130,3 +130,36 @@ def test_autotune_sets_table_and_keeps_results():
     assert labs.tune_get(L)[:2] == (lanes, lf) and labs.tune_get(L)[2]
     tuned = labs.walks_batch([dict(L=L, n_walks=512, walk_len=400, seed=3)])[0]
     _assert_same(tuned, base)
+
+
+def test_class_groups_sequential_and_concurrent_agree():
+    """A batch spanning kernels of different occupancy runs as several
+    launches; with a workspace holding every group's grid at once the groups
+    run concurrently.  Both equal the standalone runs, eagerly and as graphs."""
+    import ctypes
+    labs = _labs()
+    specs = [dict(L=L, n_walks=n, walk_len=900, seed=s, lanes_per_walk=4)
+             for L, n, s in [(301, 300, 1), (261, 128, 2), (201, 200, 3), (131, 256, 4), (67, 129, 5)]]
+    alone = [_standalone(sp) for sp in specs]
+    outs = [labs._alloc_outputs(sp["L"], sp["n_walks"], sp["walk_len"], 0) for sp in specs]
+    nb = labs.U64(0)
+    labs._check(labs.lib().labs_batch_workspace_bytes(labs.make_instances(specs, outs), len(specs),
+                                                      ctypes.byref(nb)))
+    seq = labs.walks_batch(specs, workspace=labs.alloc_workspace(nb.value))
+    conc_ws = labs.alloc_workspace(nb.value * 3)          # room for every group's grid at once
+    conc = labs.walks_batch(specs, workspace=conc_ws)
+    torch.cuda.synchronize()
+    for a, b, c in zip(seq, conc, alone):
+        _assert_same(a, c)
+        _assert_same(b, c)
+    g = labs.BatchGraph(specs, workspace=conc_ws)
+    for _ in range(2):
+        for r in g.results:
+            for t in r.values():
+                t.zero_()
+        torch.cuda.synchronize()
+        res = g.launch()
+        torch.cuda.synchronize()
+        for a, c in zip(res, alone):
+            _assert_same(a, c)
+    g.close()
