@@ -250,6 +250,45 @@ def run_solve_target(L: int, target: int, time_limit: float, walks: int, seed: i
             "seconds": r["seconds"]}
 
 
+A100_DERIVED_EVALS_PER_S = 5.5e9    # sokol on an A100, L = 225..247 (from Eq. 7, the lambda model and Table 1)
+
+
+def run_paper_regime(Ls, walks: int, rounds: int, warmup: int):
+    """The paper's own regime (Sec. 4): rounds of fresh walks of 8 D moves each,
+    timed per round including the visited-table clears and the initial energies,
+    reported in the paper's evaluation count (D - 1 per move, Alg. 1)."""
+    import torch
+    from paper_2210_15962_amd import labs
+    out = []
+    for L in Ls:
+        D = (L + 1) // 2
+        wl = 8 * D
+        plan = labs.make_plan()
+        ws = labs.alloc_workspace(labs.workspace_bytes(L, walks, wl, plan))
+        for w in range(warmup):
+            labs.walks(L, walks, wl, seed=10_000 + w, plan=plan, workspace=ws)
+        torch.cuda.synchronize()
+        stream = torch.cuda.current_stream()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        steps, ms = 0, 0.0
+        for r in range(rounds):
+            ev0.record(stream)
+            res = labs.walks(L, walks, wl, seed=r * walks, plan=plan, workspace=ws)
+            ev1.record(stream)
+            ev1.synchronize()
+            ms += ev0.elapsed_time(ev1)
+            steps += int(res["steps_done"].sum().item())
+        del ws
+        torch.cuda.empty_cache()
+        sps = steps / (ms / 1e3)
+        out.append({"workload": f"paper regime: L={L}, rounds of {walks} walks x 8D={wl} moves",
+                    "L": L, "walks_per_round": walks, "walk_len": wl, "rounds": rounds,
+                    "ms_per_round": ms / rounds, "walk_steps_per_s": sps,
+                    "paper_evals_per_s": sps * (D - 1), "neighbour_evals_per_s": sps * D,
+                    "vs_a100_derived": sps * (D - 1) / A100_DERIVED_EVALS_PER_S})
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -273,6 +312,9 @@ def main():
     ap.add_argument("--solve-time-limit", type=float, default=600.0)
     ap.add_argument("--solve-walks", type=int, default=262144)
     ap.add_argument("--solve-seeds", type=str, default="0")
+    ap.add_argument("--paper-regime", type=str, default="",
+                    help="comma-separated L: rounds of fresh 8D-move walks (Sec. 4) only")
+    ap.add_argument("--paper-walks", type=int, default=262144)
     ap.add_argument("--mixed-batch", action="store_true",
                     help="256-instance mixed-L batch (hipGraph replays) only, default then autotuned")
     args = ap.parse_args()
@@ -290,6 +332,12 @@ def main():
         for sd in [int(x) for x in args.solve_seeds.split(",")]:
             print(json.dumps(run_solve_target(int(Ls), int(Es), args.solve_time_limit, args.solve_walks, sd)),
                   flush=True)
+        return
+
+    if args.paper_regime:
+        for r in run_paper_regime([int(x) for x in args.paper_regime.split(",")], args.paper_walks,
+                                  args.steps, args.warmup):
+            print(json.dumps(r), flush=True)
         return
 
     if args.mixed_batch:

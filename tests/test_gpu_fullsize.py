@@ -102,3 +102,28 @@ def test_config3_L151_65536_walks_131072_moves_bench_plan():
     ref = O.walks(L, keys[idx], prefix)
     np.testing.assert_array_equal(short["best_E"].cpu().numpy(), ref["best_E"])
     np.testing.assert_array_equal(_u64(short["digest"]), ref["digest"])
+
+
+def test_paper_regime_L247_8D_moves():
+    """The paper's regime (Sec. 4): 262,144 fresh walks of 8 D = 992 moves at
+    L = 247, timed by the paper-regime bench leg; whole walks checked against
+    the oracle on a sample, properties on all."""
+    labs = _labs()
+    L, n = 247, 262144
+    D = (L + 1) // 2
+    wl = 8 * D
+    plan = labs.make_plan()
+    ws = labs.alloc_workspace(labs.workspace_bytes(L, n, wl, plan))
+    res = labs.walks(L, n, wl, seed=0, plan=plan, workspace=ws)
+    torch.cuda.synchronize()
+    del ws
+    torch.cuda.empty_cache()
+    best, E_best = check_best_energies(L, res)
+    sd = res["steps_done"].cpu().numpy()
+    assert (sd == wl).all()                         # no walk is trapped at 8 D moves
+    keys = O.starts(L, n, 0)
+    idx = I.sample_indices(n, 2, 2, seed=4)
+    ref = O.walks(L, keys[idx], wl)
+    np.testing.assert_array_equal(E_best[idx], ref["best_E"])
+    np.testing.assert_array_equal(best[idx], ref["best_seq"])
+    np.testing.assert_array_equal(_u64(res["digest"])[idx], ref["digest"])
