@@ -43,6 +43,18 @@ def random_start_keys(L: int, n: int, seed: int) -> np.ndarray:
     return words
 
 
+def random_full_keys(L: int, n: int, seed: int) -> np.ndarray:
+    """n uniform packed whole sequences of length L (uint64 [n, ceil(L/64)], bits above L zero)."""
+    W = (L + 63) // 64
+    words = _rng(seed).integers(0, 2**63, size=(n, W), dtype=np.int64).astype(np.uint64)
+    words |= _rng(seed + 1).integers(0, 2, size=(n, W), dtype=np.int64).astype(np.uint64) << np.uint64(63)
+    for t in range(W):
+        bits = L - 64 * t
+        if bits < 64:
+            words[:, t] &= np.uint64((1 << bits) - 1)
+    return words
+
+
 def odd_lengths(n: int, lo: int, hi: int, seed: int) -> np.ndarray:
     """n odd lengths drawn uniformly from {lo, lo+2, ..., hi} (lo, hi odd)."""
     k = (hi - lo) // 2 + 1

@@ -20,6 +20,10 @@ Functions and the passage each follows (Boskovic, Herzog & Brest, arXiv
   first half of a sequence (first free bit = most significant of D bits).
 * ``nses_limit`` / ``optimality_probability`` -- Eq. 6 and Eq. 7 with the
   lambda model of Sec. 4.1.
+* ``full_walk`` / ``full_walks`` / ``full_starts`` / ``full_bruteforce`` --
+  the whole search space (the sokol_full solver of Sec. 5's future work):
+  the same walk rules (Eq. 3, Alg. 2) over all 2^L sequences of any length L,
+  a neighbour negating one of the L positions, energies from Eq. 1.
 """
 from __future__ import annotations
 
@@ -77,6 +81,17 @@ def lib():
         L.orc_walks.restype = I32
         L.orc_bruteforce.argtypes = [I32, P, P, P, P]
         L.orc_bruteforce.restype = I32
+        L.orc_full_l_max.restype = I32
+        L.orc_full_starts.argtypes = [I32, I64, U64, P]
+        L.orc_full_starts.restype = I32
+        L.orc_full_energy_packed.argtypes = [P, I32]
+        L.orc_full_energy_packed.restype = I64
+        L.orc_full_walk.argtypes = [I32, P, I64, P, P, P, P, P, P]
+        L.orc_full_walk.restype = I32
+        L.orc_full_walks.argtypes = [I32, P, I64, I64, P, P, P, P, I32]
+        L.orc_full_walks.restype = I32
+        L.orc_full_bruteforce.argtypes = [I32, P, P, P, P]
+        L.orc_full_bruteforce.restype = I32
         _lib = L
     return _lib
 
@@ -259,3 +274,95 @@ def nses_limit(L: int, P: float = 0.99, N: int = 100) -> float:
 def optimality_probability(L: int, nses_total: float) -> float:
     """Eq. 7: P(S_best) = 1 - exp(-lambda * sum of NSEs over the runs)."""
     return 1.0 - math.exp(-lambda_model(L) * nses_total)
+
+
+# ---- the whole search space --------------------------------------------------
+
+def full_key_words(L: int) -> int:
+    return (L + 63) // 64
+
+
+def full_l_max() -> int:
+    return int(lib().orc_full_l_max())
+
+
+def full_starts(L: int, n_walks: int, seed: int) -> np.ndarray:
+    """Seeded uniform whole sequences: W = ceil(L/64) words per walk."""
+    out = np.zeros((n_walks, full_key_words(L)), dtype=np.uint64)
+    if lib().orc_full_starts(L, n_walks, seed & 0xFFFFFFFFFFFFFFFF, _ptr(out)) != 0:
+        raise ValueError("invalid arguments")
+    return out
+
+
+def full_energy_packed(key, L: int) -> int:
+    """Eq. 1 energy of a packed whole sequence (bit i-1 = s_i, 1 means -1)."""
+    k = np.ascontiguousarray(np.asarray(key, dtype=np.uint64).reshape(-1))
+    if k.size < full_key_words(L):
+        raise ValueError("key too short")
+    e = lib().orc_full_energy_packed(_ptr(k), L)
+    if e < 0:
+        raise ValueError("invalid L")
+    return int(e)
+
+
+def full_pack(s) -> np.ndarray:
+    """Pack a +-1 sequence (bit i-1 = s_i, 1 means -1)."""
+    return pack(s)
+
+
+def full_unpack(key, L: int) -> np.ndarray:
+    k = np.asarray(key, dtype=np.uint64).reshape(-1)
+    s = np.ones(L, dtype=np.int8)
+    for i in range(L):
+        if (int(k[i // 64]) >> (i % 64)) & 1:
+            s[i] = -1
+    return s
+
+
+def full_walk(L: int, start, walk_len: int, trace: bool = True) -> WalkResult:
+    """One self-avoiding walk over the whole space from a packed sequence."""
+    W = full_key_words(L)
+    st = np.ascontiguousarray(np.asarray(start, dtype=np.uint64).reshape(-1)[:W])
+    bE = np.zeros(1, dtype=np.int64)
+    bs = np.zeros(W, dtype=np.uint64)
+    sd = np.zeros(1, dtype=np.int64)
+    dg = np.zeros(1, dtype=np.uint64)
+    tj = np.zeros(max(walk_len, 1), dtype=np.int16) if trace else None
+    tE = np.zeros(max(walk_len, 1), dtype=np.int32) if trace else None
+    rc = lib().orc_full_walk(L, _ptr(st), walk_len, _ptr(bE), _ptr(bs), _ptr(sd), _ptr(dg),
+                             _ptr(tj) if trace else None, _ptr(tE) if trace else None)
+    if rc != 0:
+        raise ValueError("invalid walk arguments")
+    steps = int(sd[0])
+    return WalkResult(int(bE[0]), bs, steps, int(dg[0]),
+                      tj[:steps].copy() if trace else None,
+                      tE[:steps].copy() if trace else None)
+
+
+def full_walks(L: int, starts_arr: np.ndarray, walk_len: int, n_threads: Optional[int] = None):
+    """Independent whole-space walks over host threads.  Returns a dict of arrays."""
+    W = full_key_words(L)
+    st = np.ascontiguousarray(np.asarray(starts_arr, dtype=np.uint64).reshape(-1, W))
+    n = st.shape[0]
+    bE = np.zeros(n, dtype=np.int64)
+    bs = np.zeros((n, W), dtype=np.uint64)
+    sd = np.zeros(n, dtype=np.int64)
+    dg = np.zeros(n, dtype=np.uint64)
+    if n_threads is None:
+        n_threads = os.cpu_count() or 1
+    rc = lib().orc_full_walks(L, _ptr(st), n, walk_len, _ptr(bE), _ptr(bs), _ptr(sd), _ptr(dg),
+                              int(n_threads))
+    if rc != 0:
+        raise ValueError("invalid walk arguments")
+    return {"best_E": bE, "best_seq": bs, "steps_done": sd, "digest": dg}
+
+
+def full_bruteforce(L: int):
+    """All 2^L sequences: (min E, number of minimisers, first minimiser, sum of all E)."""
+    mn = np.zeros(1, dtype=np.int64)
+    cnt = np.zeros(1, dtype=np.int64)
+    first = np.zeros(1, dtype=np.uint64)
+    tot = np.zeros(1, dtype=np.int64)
+    if lib().orc_full_bruteforce(L, _ptr(mn), _ptr(cnt), _ptr(first), _ptr(tot)) != 0:
+        raise ValueError("L out of brute-force range")
+    return int(mn[0]), int(cnt[0]), int(first[0]), int(tot[0])
