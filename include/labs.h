@@ -155,6 +155,37 @@ int32_t labs_walks(const uint64_t *starts, int32_t L, int64_t n_walks,
                    void *workspace, uint64_t ws_bytes, const labs_plan *plan,
                    void *stream);
 
+/*
+ * Whole search space (the sokol_full solver that Sec. 5 names as future
+ * work): the walks of labs_walks over all 2^L binary sequences of any length
+ * L, 3 <= L <= labs_full_l_max() (192), even or odd.  The pivot is the whole
+ * sequence, packed in W = ceil(L/64) words (bit i-1 = s_i, 1 means -1, bits
+ * at L and above zero); a neighbour negates one sequence position, so every
+ * move scores all L neighbours by Eq. 1 (computed incrementally, exactly) and
+ * moves to the lowest-energy one not yet visited, ties broken to the lowest
+ * position i; a walk whose L neighbours are all visited stops early.  Best
+ * tracking, digest (over (i, E) per move) and traces are as in labs_walks,
+ * with trace_j holding the position i (1-based).  Seeded starts: word t of
+ * walk w is mix64(seed + 0x9E3779B97F4A7C15 * (w*W + t + 1)) masked to L bits.
+ *   labs_full_key_words: W for a valid L, else 0.
+ *   labs_full_walks_workspace_bytes: workspace for all n_walks visited tables
+ *     at once (smaller workspaces run the walks in chunks, down to one table).
+ *   labs_full_walks: arguments, ownership and layout as labs_walks (device
+ *     pointers, asynchronous on stream, workspace contents unspecified on
+ *     exit); plan->lanes_per_walk must be 0 or 4.
+ * Errors: LABS_EINVAL (L outside [3, 192], n_walks < 0, walk_len < 0 or above
+ * 2^31, NULL required pointer, bad plan, workspace below one table),
+ * LABS_EDEVICE (launch failure).
+ */
+int32_t labs_full_l_max(void);
+int32_t labs_full_key_words(int32_t L);
+int32_t labs_full_walks_workspace_bytes(int32_t L, int64_t n_walks, int64_t walk_len,
+                                        const labs_plan *plan, uint64_t *bytes);
+int32_t labs_full_walks(const uint64_t *starts, int32_t L, int64_t n_walks,
+                        int64_t walk_len, uint64_t seed, const labs_walk_out *out,
+                        void *workspace, uint64_t ws_bytes, const labs_plan *plan,
+                        void *stream);
+
 
 /*
  * Mixed-length batches (several instances of different L in one launch).

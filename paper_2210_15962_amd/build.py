@@ -32,13 +32,21 @@ def build(verbose: bool = True) -> str:
     bdir = os.path.join(HERE, "_build")
     os.makedirs(bdir, exist_ok=True)
     objs = []
-    kern_obj = os.path.join(bdir, "labs_kernels.o")
     extra = []
     if os.environ.get("LABS_SAVE_TEMPS"):
         extra = ["-save-temps=obj"]
-    _run([hipcc, "-x", "hip", f"--offload-arch={ARCH}", *COMMON, *DEVICE_FLAGS, *extra, "-c",
-          os.path.join(CSRC, "labs_kernels.hip"), "-o", kern_obj])
-    objs.append(kern_obj)
+    # The two device translation units compile in parallel (each takes minutes).
+    procs = []
+    for src in ("labs_kernels.hip", "labs_full.hip"):
+        obj = os.path.join(bdir, src.replace(".hip", ".o"))
+        cmd = [hipcc, "-x", "hip", f"--offload-arch={ARCH}", *COMMON, *DEVICE_FLAGS, *extra, "-c",
+               os.path.join(CSRC, src), "-o", obj]
+        print(" ".join(cmd), flush=True)
+        procs.append((subprocess.Popen(cmd), cmd))
+        objs.append(obj)
+    for proc, cmd in procs:
+        if proc.wait() != 0:
+            raise subprocess.CalledProcessError(proc.returncode, cmd)
     for host_src in ("labs_api.cpp", "labs_serve.cpp", "labs_solve.cpp"):
         obj = os.path.join(bdir, host_src.replace(".cpp", ".o"))
         _run([hipcc, *COMMON, "-D__HIP_PLATFORM_AMD__", "-c", os.path.join(CSRC, host_src),

@@ -42,8 +42,9 @@ struct Plan {
   int64_t max_conc;      // user bound on resident walks (0 = none)
 };
 
-int32_t make_plan(int32_t L, int64_t walk_len, const labs_plan *p, Plan &out) {
-  if (!valid_skew_L(L)) return fail(LABS_EINVAL, "L=%d: need odd L with 3 <= L <= %d", L, lsaw::kLMax);
+// Plan fields from the caller's labs_plan and the visited-table size for
+// walk_len moves with entries of entry_bytes.
+int32_t plan_tables(int entry_bytes, int64_t walk_len, const labs_plan *p, Plan &out) {
   if (walk_len < 0) return fail(LABS_EINVAL, "walk_len=%lld must be >= 0", (long long)walk_len);
   if (walk_len > (int64_t)1 << 31) return fail(LABS_EINVAL, "walk_len=%lld exceeds 2^31", (long long)walk_len);
   out.G = 0;
@@ -60,7 +61,7 @@ int32_t make_plan(int32_t L, int64_t walk_len, const labs_plan *p, Plan &out) {
     if (p->load_factor != 0.0) out.alpha = p->load_factor;
     out.max_conc = p->max_concurrent;
   }
-  const int epb = lsaw::kBucketBytes / lsaw::entry_bytes_for(L);
+  const int epb = lsaw::kBucketBytes / entry_bytes;
   const double keys = (double)walk_len + 1.0;
   double nb = keys / (epb * out.alpha);
   uint64_t n_buckets = (uint64_t)nb;
@@ -71,6 +72,25 @@ int32_t make_plan(int32_t L, int64_t walk_len, const labs_plan *p, Plan &out) {
   if (n_buckets >= ((uint64_t)1 << 32)) return fail(LABS_EINVAL, "visited table too large");
   out.n_buckets = (uint32_t)n_buckets;
   out.table_bytes = n_buckets * (uint64_t)lsaw::kBucketBytes;
+  return LABS_OK;
+}
+
+int32_t make_plan(int32_t L, int64_t walk_len, const labs_plan *p, Plan &out) {
+  if (!valid_skew_L(L)) return fail(LABS_EINVAL, "L=%d: need odd L with 3 <= L <= %d", L, lsaw::kLMax);
+  return plan_tables(lsaw::entry_bytes_for(L), walk_len, p, out);
+}
+
+bool valid_full_L(int32_t L) { return L >= 3 && L <= lsaw::kFullLMax; }
+
+// Whole-space walks run four lanes per walk.
+int32_t make_full_plan(int32_t L, int64_t walk_len, const labs_plan *p, Plan &out) {
+  if (!valid_full_L(L)) return fail(LABS_EINVAL, "L=%d: need 3 <= L <= %d", L, lsaw::kFullLMax);
+  const int32_t rc = plan_tables(lsaw::full_entry_bytes_for(L), walk_len, p, out);
+  if (rc != LABS_OK) return rc;
+  const int G = lsaw::full_lanes_per_walk();
+  if (out.G != 0 && out.G != G)
+    return fail(LABS_EINVAL, "lanes_per_walk=%d: whole-space walks use 0 or %d", out.G, G);
+  out.G = G;
   return LABS_OK;
 }
 
@@ -227,6 +247,71 @@ int32_t labs_walks(const uint64_t *starts, int32_t L, int64_t n_walks, int64_t w
     w.lanes_per_walk = G;
     hipError_t e = lsaw::launch_walks(w, st);
     if (e != hipSuccess) return fail(LABS_EDEVICE, "walk launch: %s", hipGetErrorString(e));
+  }
+  return ok();
+}
+
+int32_t labs_full_l_max(void) { return lsaw::kFullLMax; }
+
+int32_t labs_full_key_words(int32_t L) { return valid_full_L(L) ? lsaw::full_key_words_for(L) : 0; }
+
+int32_t labs_full_walks_workspace_bytes(int32_t L, int64_t n_walks, int64_t walk_len,
+                                        const labs_plan *plan, uint64_t *bytes) {
+  if (!bytes) return fail(LABS_EINVAL, "NULL bytes");
+  if (n_walks < 0) return fail(LABS_EINVAL, "n_walks must be >= 0");
+  Plan p;
+  int32_t rc = make_full_plan(L, walk_len, plan, p);
+  if (rc != LABS_OK) return rc;
+  int64_t conc = n_walks;
+  if (p.max_conc > 0) conc = std::min(conc, p.max_conc);
+  *bytes = (uint64_t)conc * p.table_bytes;
+  return ok();
+}
+
+int32_t labs_full_walks(const uint64_t *starts, int32_t L, int64_t n_walks, int64_t walk_len,
+                        uint64_t seed, const labs_walk_out *out, void *workspace, uint64_t ws_bytes,
+                        const labs_plan *plan, void *stream) {
+  Plan p;
+  int32_t rc = make_full_plan(L, walk_len, plan, p);
+  if (rc != LABS_OK) return rc;
+  if (n_walks < 0) return fail(LABS_EINVAL, "n_walks=%lld must be >= 0", (long long)n_walks);
+  if (!out) return fail(LABS_EINVAL, "NULL out");
+  if (n_walks == 0) return ok();
+  if (!out->best_seq || !out->best_E || !out->steps_done)
+    return fail(LABS_EINVAL, "best_seq, best_E and steps_done are required");
+  if (out->n_trace < 0 || out->n_trace > n_walks) return fail(LABS_EINVAL, "n_trace out of range");
+  if (out->n_trace > 0 && (!out->trace_j || !out->trace_E))
+    return fail(LABS_EINVAL, "trace buffers required when n_trace > 0");
+  if (!workspace) return fail(LABS_EINVAL, "NULL workspace");
+  if (ws_bytes < p.table_bytes)
+    return fail(LABS_EINVAL, "workspace of %llu bytes is below the minimum %llu",
+                (unsigned long long)ws_bytes, (unsigned long long)p.table_bytes);
+  int64_t conc = (int64_t)std::min<uint64_t>((uint64_t)n_walks, ws_bytes / p.table_bytes);
+  if (p.max_conc > 0) conc = std::min(conc, p.max_conc);
+  hipStream_t st = as_stream(stream);
+  for (int64_t begin = 0; begin < n_walks; begin += conc) {
+    const int64_t cnt = std::min(conc, n_walks - begin);
+    lsaw::WalkLaunch w;
+    w.starts = starts;
+    w.seed = seed;
+    w.L = L;
+    w.walk_begin = begin;
+    w.n_walks = cnt;
+    w.walk_len = walk_len;
+    w.best_seq = out->best_seq;
+    w.best_E = out->best_E;
+    w.steps_done = out->steps_done;
+    w.digest = out->digest;
+    w.trace_j = out->trace_j;
+    w.trace_E = out->trace_E;
+    w.n_trace = out->n_trace;
+    w.cap_steps = out->cap_steps;
+    w.tables = static_cast<uint8_t *>(workspace);
+    w.table_bytes = p.table_bytes;
+    w.n_buckets = p.n_buckets;
+    w.lanes_per_walk = p.G;
+    hipError_t e = lsaw::launch_full_walks(w, st);
+    if (e != hipSuccess) return fail(LABS_EDEVICE, "whole-space walk launch: %s", hipGetErrorString(e));
   }
   return ok();
 }

@@ -1,0 +1,216 @@
+// labs_device.h -- device helpers shared by the walk kernels of liblabs.so
+// (skew-symmetric space and whole space): bit and lane-exchange primitives,
+// the exact visited table with its incremental hash, and the per-lane top-K.
+// Not part of the public ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <type_traits>
+#include "labs_internal.h"
+
+namespace lsaw {
+
+template <int I, int N, class F>
+__device__ __forceinline__ void static_for(F &&f) {
+  if constexpr (I < N) {
+    f(std::integral_constant<int, I>{});
+    static_for<I + 1, N>(f);
+  }
+}
+
+// v[i] for a small register array and a runtime index (select chain, no scratch).
+template <int N>
+__device__ __forceinline__ uint32_t sel(const uint32_t (&v)[N], int i) {
+  uint32_t r = v[0];
+#pragma unroll
+  for (int k = 1; k < N; ++k) r = (i == k) ? v[k] : r;
+  return r;
+}
+
+// ---------------------------------------------------------------------------
+// Small helpers
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint64_t mix64(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+__device__ __forceinline__ uint32_t popc_add(uint32_t x, uint32_t acc) {
+  uint32_t r;
+  asm("v_bcnt_u32_b32 %0, %1, %2" : "=v"(r) : "v"(x), "v"(acc));
+  return r;
+}
+
+// Median of three unsigned values (one v_med3_u32).
+__device__ __forceinline__ uint32_t umed3(uint32_t a, uint32_t b, uint32_t c) {
+  uint32_t r;
+  asm("v_med3_u32 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+  return r;
+}
+
+// (a << S) + b as one v_lshl_add_u32 (kept as a chain, not reassociated).
+template <int S>
+__device__ __forceinline__ uint32_t lshl_add(uint32_t a, uint32_t b) {
+  uint32_t r;
+  asm("v_lshl_add_u32 %0, %1, %2, %3" : "=v"(r) : "v"(a), "I"(S), "v"(b));
+  return r;
+}
+
+__device__ __forceinline__ uint32_t funnel(uint32_t hi, uint32_t lo, uint32_t sh) {
+  return __builtin_amdgcn_alignbit(hi, lo, sh);
+}
+
+// Min / max over the G consecutive lanes that cooperate on one walk, with DPP
+// lane exchanges inside the VALU (no LDS round trip): quad permutations swap
+// neighbours and pairs within each group of four lanes, and the half-row
+// mirror (lane i <-> 7 - i within eight lanes) joins two quads.
+constexpr int kDppQuadSwap1 = 0xB1;      // quad_perm [1, 0, 3, 2]
+constexpr int kDppQuadSwap2 = 0x4E;      // quad_perm [2, 3, 0, 1]
+constexpr int kDppHalfMirror = 0x141;    // row_half_mirror
+
+template <int CTRL>
+__device__ __forceinline__ uint32_t dpp(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, 0xF, 0xF, false);
+}
+template <int G>
+__device__ __forceinline__ uint32_t group_min(uint32_t v) {
+  if constexpr (G >= 2) v = min(v, dpp<kDppQuadSwap1>(v));
+  if constexpr (G >= 4) v = min(v, dpp<kDppQuadSwap2>(v));
+  if constexpr (G >= 8) v = min(v, dpp<kDppHalfMirror>(v));
+  return v;
+}
+template <int G>
+__device__ __forceinline__ uint32_t group_max(uint32_t v) {
+  if constexpr (G >= 2) v = max(v, dpp<kDppQuadSwap1>(v));
+  if constexpr (G >= 4) v = max(v, dpp<kDppQuadSwap2>(v));
+  if constexpr (G >= 8) v = max(v, dpp<kDppHalfMirror>(v));
+  return v;
+}
+// Same with the group size known only at run time (G == 0), wave-uniform Gl.
+template <int G>
+__device__ __forceinline__ uint32_t grp_min(uint32_t v, int Gl) {
+  if constexpr (G > 0) {
+    return group_min<G>(v);
+  } else {
+    if (Gl >= 2) v = min(v, dpp<kDppQuadSwap1>(v));
+    if (Gl >= 4) v = min(v, dpp<kDppQuadSwap2>(v));
+    if (Gl >= 8) v = min(v, dpp<kDppHalfMirror>(v));
+    return v;
+  }
+}
+template <int G>
+__device__ __forceinline__ uint32_t grp_max(uint32_t v, int Gl) {
+  if constexpr (G > 0) {
+    return group_max<G>(v);
+  } else {
+    if (Gl >= 2) v = max(v, dpp<kDppQuadSwap1>(v));
+    if (Gl >= 4) v = max(v, dpp<kDppQuadSwap2>(v));
+    if (Gl >= 8) v = max(v, dpp<kDppHalfMirror>(v));
+    return v;
+  }
+}
+
+__host__ __device__ constexpr int clog2(int v) { int b = 0; while ((1 << b) < v) ++b; return b; }
+
+__device__ __forceinline__ uint32_t prefix_mask(int n, int w) {
+  const int len = n - 32 * w;
+  return len >= 32 ? 0xFFFFFFFFu : (len <= 0 ? 0u : ((1u << len) - 1u));
+}
+
+constexpr uint32_t kKeyMax = 0xFFFFFFFFu;
+constexpr int32_t kBias = 1 << 23;      // bias of the scaled energy change inside a candidate key
+
+// ---------------------------------------------------------------------------
+// Visited table
+// ---------------------------------------------------------------------------
+struct Key3 { uint64_t w0, w1, w2; };
+
+// Bucket of a key: an XOR-linear (Zobrist) hash -- the XOR of one random
+// 32-bit word per set key bit -- mapped onto [0, n_buckets) by a
+// multiply-high.  A walk keeps the hash of its pivot, so the hash of any
+// neighbour is one XOR away.  The table stores full keys, so the hash only
+// decides where a key is looked for, never whether it is found.
+__device__ __forceinline__ uint32_t zobrist_word(int jm1) {
+  return (uint32_t)(mix64(0xA0761D6478BD642Full + (uint64_t)jm1) >> 32);
+}
+__device__ __forceinline__ uint32_t bucket_of_hash(uint32_t h, uint32_t n_buckets) {
+  return __umulhi(h, n_buckets);
+}
+
+// Scan one bucket.  Returns 2 = key present, 1 = absent (slot = first free
+// entry), 0 = bucket full without the key.  Entries fill in order and are
+// never deleted, so a present key lies before the first free entry.  No
+// early exits: the four (or two) entries are tested with selects.
+__device__ __forceinline__ int scan_bucket(const uint8_t *bucket, const Key3 &k, bool e32,
+                                           uint32_t &slot) {
+  const uint4 *q = reinterpret_cast<const uint4 *>(bucket);
+  const uint4 v0 = q[0], v1 = q[1], v2 = q[2], v3 = q[3];
+  const uint32_t k0l = (uint32_t)k.w0, k0h = (uint32_t)(k.w0 >> 32);
+  const uint32_t k1l = (uint32_t)k.w1, k1h = (uint32_t)(k.w1 >> 32);
+  bool found;
+  uint32_t free_slot;
+  if (!e32) {
+    auto eq = [&](const uint4 &e) {
+      return e.x == k0l && e.y == k0h && e.z == k1l && e.w == (k1h | 0x80000000u);
+    };
+    found = eq(v0) || eq(v1) || eq(v2) || eq(v3);
+    free_slot = (v0.w >> 31) == 0u ? 0u : (v1.w >> 31) == 0u ? 16u :
+                (v2.w >> 31) == 0u ? 32u : (v3.w >> 31) == 0u ? 48u : 64u;
+  } else {
+    const uint32_t k2l = (uint32_t)k.w2, k2h = (uint32_t)(k.w2 >> 32);
+    auto eq = [&](const uint4 &lo, const uint4 &hi) {
+      return lo.x == k0l && lo.y == k0h && lo.z == k1l && lo.w == k1h && hi.x == k2l &&
+             hi.y == k2h && hi.z != 0u;
+    };
+    found = eq(v0, v1) || eq(v2, v3);
+    free_slot = v1.z == 0u ? 0u : v3.z == 0u ? 32u : 64u;
+  }
+  slot = free_slot;
+  return found ? 2 : (free_slot < 64u ? 1 : 0);
+}
+
+__device__ __forceinline__ void store_entry(uint8_t *p, const Key3 &k, bool e32) {
+  if (!e32) {
+    uint4 v;
+    v.x = (uint32_t)k.w0; v.y = (uint32_t)(k.w0 >> 32);
+    v.z = (uint32_t)k.w1; v.w = (uint32_t)(k.w1 >> 32) | 0x80000000u;
+    *reinterpret_cast<uint4 *>(p) = v;
+  } else {
+    uint4 a, b;
+    a.x = (uint32_t)k.w0; a.y = (uint32_t)(k.w0 >> 32);
+    a.z = (uint32_t)k.w1; a.w = (uint32_t)(k.w1 >> 32);
+    b.x = (uint32_t)k.w2; b.y = (uint32_t)(k.w2 >> 32); b.z = 1u; b.w = 0u;
+    reinterpret_cast<uint4 *>(p)[0] = a;
+    reinterpret_cast<uint4 *>(p)[1] = b;
+  }
+}
+
+__device__ __forceinline__ Key3 flip_key(const Key3 &k, uint32_t jm1) {
+  Key3 r = k;
+  const uint64_t bit = 1ull << (jm1 & 63u);
+  const uint32_t w = jm1 >> 6;
+  r.w0 ^= (w == 0) ? bit : 0ull;
+  r.w1 ^= (w == 1) ? bit : 0ull;
+  r.w2 ^= (w == 2) ? bit : 0ull;
+  return r;
+}
+
+__device__ __forceinline__ uint32_t key_bit(const Key3 &k, int jm1) {
+  const uint64_t w = (jm1 >> 6) == 0 ? k.w0 : (jm1 >> 6) == 1 ? k.w1 : k.w2;
+  return (uint32_t)((w >> (jm1 & 63)) & 1ull);
+}
+
+template <int K>
+__device__ __forceinline__ void topk_insert(uint32_t (&tk)[K], uint32_t x) {
+  if constexpr (K == 1) {
+    tk[0] = min(tk[0], x);
+  } else {
+    // Sorted insertion: new[i] = median(old[i-1], old[i], x), new[0] = min.
+#pragma unroll
+    for (int i = K - 1; i >= 1; --i) tk[i] = umed3(tk[i - 1], tk[i], x);   // tk sorted
+    tk[0] = min(tk[0], x);
+  }
+}
+
+}  // namespace lsaw

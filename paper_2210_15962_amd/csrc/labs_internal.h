@@ -18,6 +18,12 @@ inline int lag_words_for(int L) { return ((L - 1) / 2 + 31) / 32; }
 // keys use 32-byte entries.
 inline int entry_bytes_for(int L) { return free_bits(L) <= 127 ? 16 : 32; }
 
+// Whole search space: keys are the L sequence bits, lags k = 1..L-1.
+constexpr int kFullLMax = 192;      // W <= 3 key words, <= 6 lag words
+inline int full_key_words_for(int L) { return (L + 63) / 64; }
+inline int full_lag_words_for(int L) { return (L - 1 + 31) / 32; }
+inline int full_entry_bytes_for(int L) { return L <= 127 ? 16 : 32; }
+
 struct WalkLaunch {
   const uint64_t *starts;   // device [n][W] or nullptr (seeded starts)
   uint64_t seed;
@@ -112,6 +118,11 @@ hipError_t launch_starts(int32_t L, int64_t n_walks, uint64_t seed, uint64_t *ou
 hipError_t launch_walks(const WalkLaunch &w, hipStream_t stream);
 // Dynamic LDS bytes the walk kernel needs for length L (0 if unsupported).
 size_t walk_lds_bytes(int32_t L);
+// Whole-space walks (labs_full.hip): lanes per walk the kernel is built for,
+// its LDS bytes for length L, and the launch (w.L is the sequence length).
+int full_lanes_per_walk();
+size_t full_walk_lds_bytes(int32_t L);
+hipError_t launch_full_walks(const WalkLaunch &w, hipStream_t stream);
 // Batch kernel of lag-word class nw (2..6; class 1 runs on the class-2 kernel).
 int batch_variant(int nw);
 size_t batch_lds_bytes(int variant);

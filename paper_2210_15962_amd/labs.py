@@ -114,6 +114,15 @@ def lib():
         L.labs_walks.argtypes = [VP, I32, I64, I64, U64, ctypes.POINTER(WalkOut), VP, U64,
                                  ctypes.POINTER(Plan), VP]
         L.labs_walks.restype = I32
+        L.labs_full_l_max.restype = I32
+        L.labs_full_key_words.argtypes = [I32]
+        L.labs_full_key_words.restype = I32
+        L.labs_full_walks_workspace_bytes.argtypes = [I32, I64, I64, ctypes.POINTER(Plan),
+                                                      ctypes.POINTER(U64)]
+        L.labs_full_walks_workspace_bytes.restype = I32
+        L.labs_full_walks.argtypes = [VP, I32, I64, I64, U64, ctypes.POINTER(WalkOut), VP, U64,
+                                      ctypes.POINTER(Plan), VP]
+        L.labs_full_walks.restype = I32
         L.labs_batch_workspace_bytes.argtypes = [ctypes.POINTER(Instance), I32, ctypes.POINTER(U64)]
         L.labs_batch_workspace_bytes.restype = I32
         L.labs_walks_batch.argtypes = [ctypes.POINTER(Instance), I32, VP, U64, VP]
@@ -291,6 +300,58 @@ def walks(L: int, n_walks: int, walk_len: int, seed: int = 0, starts_t=None, n_t
     _check(lib().labs_walks(_dptr(starts_t), L, n_walks, walk_len, seed & 0xFFFFFFFFFFFFFFFF,
                             ctypes.byref(out), _dptr(workspace), workspace.numel(),
                             ctypes.byref(plan) if plan else None, _stream_handle(stream)))
+    return res
+
+
+# ------------------------------------------------------------- whole space
+def full_l_max() -> int:
+    return int(lib().labs_full_l_max())
+
+
+def full_key_words(L: int) -> int:
+    return int(lib().labs_full_key_words(L))
+
+
+def full_workspace_bytes(L: int, n_walks: int, walk_len: int, plan: Optional[Plan] = None) -> int:
+    b = U64(0)
+    _check(lib().labs_full_walks_workspace_bytes(L, n_walks, walk_len,
+                                                 ctypes.byref(plan) if plan else None, ctypes.byref(b)))
+    return int(b.value)
+
+
+def full_walks(L: int, n_walks: int, walk_len: int, seed: int = 0, starts_t=None, n_trace: int = 0,
+               plan: Optional[Plan] = None, workspace=None, digest: bool = True, stream=None,
+               device="cuda", cap_steps: bool = False):
+    """Self-avoiding walks over all 2^L sequences of length L (labs_full_walks);
+    returns a dict of CUDA tensors laid out as walks() does, with W = ceil(L/64)
+    key words holding the whole sequence and trace_j the position flipped."""
+    import torch
+    W = full_key_words(L)
+    if W == 0:
+        raise LabsError(LABS_EINVAL, f"invalid L={L}")
+    if starts_t is not None:
+        if starts_t.dtype != torch.int64 or tuple(starts_t.shape) != (n_walks, W) or not starts_t.is_cuda:
+            raise ValueError("starts must be an int64 CUDA tensor of shape (n_walks, W)")
+        starts_t = starts_t.contiguous()
+    if workspace is None:
+        workspace = alloc_workspace(full_workspace_bytes(L, n_walks, walk_len, plan), device=device)
+    res = {
+        "best_seq": torch.empty((n_walks, W), dtype=torch.int64, device=device),
+        "best_E": torch.empty(n_walks, dtype=torch.int32, device=device),
+        "steps_done": torch.empty(n_walks, dtype=torch.int64, device=device),
+        "digest": torch.empty(n_walks, dtype=torch.int64, device=device) if digest else None,
+    }
+    if n_trace:
+        res["trace_j"] = torch.zeros((n_trace, walk_len), dtype=torch.int16, device=device)
+        res["trace_E"] = torch.zeros((n_trace, walk_len), dtype=torch.int32, device=device)
+    if cap_steps:
+        res["cap_steps"] = torch.zeros((n_walks, 4), dtype=torch.int32, device=device)
+    out = WalkOut(_dptr(res["best_seq"]), _dptr(res["best_E"]), _dptr(res["steps_done"]),
+                  _dptr(res["digest"]), _dptr(res.get("trace_j")), _dptr(res.get("trace_E")),
+                  n_trace, _dptr(res.get("cap_steps")))
+    _check(lib().labs_full_walks(_dptr(starts_t), L, n_walks, walk_len, seed & 0xFFFFFFFFFFFFFFFF,
+                                 ctypes.byref(out), _dptr(workspace), workspace.numel(),
+                                 ctypes.byref(plan) if plan else None, _stream_handle(stream)))
     return res
 
 

@@ -205,3 +205,34 @@ def test_solve_validation_before_any_launch():
     assert lib.labs_solve(27, ctypes.byref(cfg), ctypes.c_void_p(1), 16, None, ctypes.byref(res)) == labs.LABS_EINVAL
     cfg.walks_per_round = 0
     assert lib.labs_solve(27, ctypes.byref(cfg), ctypes.c_void_p(1), 1 << 40, None, ctypes.byref(res)) == labs.LABS_EINVAL
+
+
+def test_full_space_sizes_and_validation_before_any_launch():
+    assert labs.full_l_max() == 192 == O.full_l_max()
+    for L in [3, 4, 63, 64, 65, 128, 129, 192]:
+        assert labs.full_key_words(L) == O.full_key_words(L)
+    for bad in [-1, 0, 1, 2, 193, 383]:
+        assert labs.full_key_words(bad) == 0
+    # 16-byte entries up to L = 127, then 32-byte entries
+    b127 = labs.full_workspace_bytes(127, 1, 1000)
+    b128 = labs.full_workspace_bytes(128, 1, 1000)
+    assert b128 >= 2 * b127 - 64 and b127 // 64 * 4 * 0.5 >= 1001
+    assert labs.full_workspace_bytes(64, 10, 100, labs.make_plan(max_concurrent=4)) == \
+        4 * labs.full_workspace_bytes(64, 1, 100)
+    lib = labs.lib()
+    out = labs.WalkOut(1, 1, 1, None, None, None, 0)
+    ws = ctypes.c_void_p(1)
+    ref = ctypes.byref
+    for bad_L in (2, 193, -5):
+        assert lib.labs_full_walks(None, bad_L, 4, 10, 0, ref(out), ws, 1 << 30, None, None) == labs.LABS_EINVAL
+    assert lib.labs_full_walks(None, 64, -1, 10, 0, ref(out), ws, 1 << 30, None, None) == labs.LABS_EINVAL
+    assert lib.labs_full_walks(None, 64, 4, -1, 0, ref(out), ws, 1 << 30, None, None) == labs.LABS_EINVAL
+    assert lib.labs_full_walks(None, 64, 4, 10, 0, None, ws, 1 << 30, None, None) == labs.LABS_EINVAL
+    assert lib.labs_full_walks(None, 64, 4, 10, 0, ref(out), None, 1 << 30, None, None) == labs.LABS_EINVAL
+    assert lib.labs_full_walks(None, 64, 4, 10, 0, ref(out), ws, 8, None, None) == labs.LABS_EINVAL
+    for G in (1, 2, 8, 3):
+        bad = labs.make_plan(lanes_per_walk=G)
+        assert lib.labs_full_walks(None, 64, 4, 10, 0, ref(out), ws, 1 << 30, ref(bad), None) == labs.LABS_EINVAL
+    tr = labs.WalkOut(1, 1, 1, None, None, None, 5)
+    assert lib.labs_full_walks(None, 64, 4, 10, 0, ref(tr), ws, 1 << 30, None, None) == labs.LABS_EINVAL
+    assert lib.labs_full_walks(None, 64, 0, 10, 0, ref(out), ws, 0, None, None) == labs.LABS_OK

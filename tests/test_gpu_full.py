@@ -1,0 +1,106 @@
+"""Whole-space walks (labs_full_walks) against the whole-space oracle: every
+walk's best energy, best sequence, move count and digest, and the traces of
+the first walks, bit-exact, over lengths that cross every lag-word, key-word
+and table-entry boundary, with ragged block tails, trapped walks, explicit
+and seeded starts, and chunked launches."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+import labs_inputs as I
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(autouse=True)
+def _announce(request):
+    print(f"\n[case] {request.node.name}", flush=True)
+    yield
+    torch.cuda.empty_cache()
+
+
+def _labs():
+    from paper_2210_15962_amd import labs
+    return labs
+
+
+def _u64(t):
+    return t.cpu().numpy().view(np.uint64)
+
+
+def _compare(L, keys, res, walk_len, n_trace=0):
+    ref = O.full_walks(L, keys, walk_len)
+    np.testing.assert_array_equal(res["best_E"].cpu().numpy(), ref["best_E"])
+    np.testing.assert_array_equal(_u64(res["best_seq"]).reshape(ref["best_seq"].shape), ref["best_seq"])
+    np.testing.assert_array_equal(res["steps_done"].cpu().numpy(), ref["steps_done"])
+    np.testing.assert_array_equal(_u64(res["digest"]), ref["digest"])
+    for i in range(n_trace):
+        r = O.full_walk(L, keys[i], walk_len)
+        np.testing.assert_array_equal(res["trace_j"][i].cpu().numpy()[: r.steps], r.trace_j)
+        np.testing.assert_array_equal(res["trace_E"][i].cpu().numpy()[: r.steps], r.trace_E)
+
+
+LENGTHS = [3, 4, 5, 8, 13, 16, 27, 32, 33, 34, 50, 63, 64, 65, 66, 96, 97, 98, 127, 128, 129,
+           150, 160, 161, 162, 191, 192]
+
+
+@pytest.mark.parametrize("L", LENGTHS)
+def test_seeded_walks_match_oracle(L):
+    labs = _labs()
+    n = 70                                          # two workgroups, the second ragged
+    walk_len = 400 if L <= 64 else (150 if L <= 128 else 60)
+    print(f"[full] L={L} n={n} walk_len={walk_len}", flush=True)
+    res = labs.full_walks(L, n, walk_len, seed=L, n_trace=2)
+    torch.cuda.synchronize()
+    _compare(L, O.full_starts(L, n, L), res, walk_len, n_trace=2)
+
+
+@pytest.mark.parametrize("L", [3, 4, 5, 6, 7])
+def test_trapped_walks(L):
+    labs = _labs()
+    n, walk_len = 64, 300                          # more moves than states
+    res = labs.full_walks(L, n, walk_len, seed=7, n_trace=4)
+    torch.cuda.synchronize()
+    sd = res["steps_done"].cpu().numpy()
+    assert (sd < (1 << L)).all()
+    _compare(L, O.full_starts(L, n, 7), res, walk_len, n_trace=4)
+
+
+@pytest.mark.parametrize("L", [20, 71, 130, 192])
+def test_explicit_starts_and_chunks(L):
+    labs = _labs()
+    n, walk_len = 200, 120
+    keys = I.random_full_keys(L, n, seed=L + 3)
+    st = torch.from_numpy(I.as_int64_keys(keys)).cuda()
+    res = labs.full_walks(L, n, walk_len, starts_t=st, n_trace=1)
+    # four chunks of at most 64 resident walks give identical results
+    plan = labs.make_plan(max_concurrent=64)
+    ws = labs.alloc_workspace(labs.full_workspace_bytes(L, 64, walk_len))
+    res2 = labs.full_walks(L, n, walk_len, starts_t=st, plan=plan, workspace=ws)
+    torch.cuda.synchronize()
+    _compare(L, keys, res, walk_len, n_trace=1)
+    np.testing.assert_array_equal(_u64(res2["digest"]), _u64(res["digest"]))
+    np.testing.assert_array_equal(res2["best_E"].cpu().numpy(), res["best_E"].cpu().numpy())
+
+
+def test_seeded_starts_equal_explicit_oracle_starts_and_walk_len_zero():
+    labs = _labs()
+    L, n = 100, 96
+    keys = O.full_starts(L, n, 11)
+    res = labs.full_walks(L, n, 0, seed=11)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(_u64(res["best_seq"]), keys)
+    assert (res["steps_done"].cpu().numpy() == 0).all()
+    np.testing.assert_array_equal(res["best_E"].cpu().numpy(),
+                                  [O.full_energy_packed(k, L) for k in keys])
+
+
+def test_cap_counts_cover_every_scan():
+    labs = _labs()
+    L, n, walk_len = 128, 256, 500
+    res = labs.full_walks(L, n, walk_len, seed=1, cap_steps=True)
+    torch.cuda.synchronize()
+    caps = res["cap_steps"].cpu().numpy().astype(np.int64)
+    np.testing.assert_array_equal(caps.sum(axis=1), res["steps_done"].cpu().numpy()
+                                  + (res["steps_done"].cpu().numpy() < walk_len))
