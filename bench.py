@@ -73,17 +73,41 @@ def ops_per_candidate(L: int) -> float:
     return ops_per_scan(L, 0) / ((L + 1) // 2)
 
 
-def kernel_source_tag() -> str:
+def full_planes_of(nw: int, w: int) -> int:
+    mx = (32 * nw + 1 - 1 - 32 * w) // 2 + 1
+    b = 0
+    while (1 << b) < mx:
+        b += 1
+    return 1 + b
+
+
+def full_ops_per_scan(L: int, cap: int = 0) -> int:
+    """Algorithmic 32-bit lane-ops of one whole-space neighbourhood scan (all L
+    positions): per lag word of a candidate's forward range one 3-input
+    bitwise op and one popcount per c plane plus one pair for the even-C
+    correction, the same for its backward range, and one pair per word of the
+    squared term; cap as in ops_per_scan."""
+    nw = (L - 1 + 31) // 32
+    pl = [full_planes_of(nw, w) if cap == 0 else min(cap, full_planes_of(nw, w)) for w in range(nw)]
+    tot = 0
+    for i in range(1, L + 1):
+        nF, nB = L - i, i - 1
+        fw, bw, q = (nF + 31) // 32, (nB + 31) // 32, (min(nF, nB) + 31) // 32
+        tot += 2 * (sum(pl[:fw]) + fw + sum(pl[:bw]) + bw + q)
+    return tot
+
+
+def kernel_source_tag(name: str = "labs_kernels.hip") -> str:
     import hashlib
-    src = os.path.join(ROOT, "paper_2210_15962_amd", "csrc", "labs_kernels.hip")
+    src = os.path.join(ROOT, "paper_2210_15962_amd", "csrc", name)
     with open(src, "rb") as f:
         return hashlib.sha1(f.read()).hexdigest()[:12]
 
 
-def load_counter_traffic(kernel_tag: str):
+def load_counter_traffic(kernel_tag: str, name: str = "walk_kernel_L151_traffic.json"):
     """HBM bytes per launch measured by rocprofv3 --pmc, if recorded for this
     kernel build (profiles/<name>.json written from the counter runs)."""
-    path = os.path.join(ROOT, "profiles", "walk_kernel_L151_traffic.json")
+    path = os.path.join(ROOT, "profiles", name)
     try:
         with open(path) as f:
             d = json.load(f)
@@ -113,6 +137,91 @@ def cpu_baseline(L: int, seconds_target: float = 15.0):
     return {"value": total / dt, "unit": "walk steps/s", "cores": cores, "kind": "oracle",
             "sample": f"{cores} walks x {steps} moves at L={L} (seed 0 starts), "
                       f"one walk per host thread, {dt:.1f} s wall"}
+
+
+def cpu_baseline_full(L: int, seconds_target: float = 15.0):
+    """The whole-space CPU oracle (untuned) on a bounded sample of the workload."""
+    from oracle import oracle as O
+    cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    cores = max(1, min(cores, 64))
+    st = O.full_starts(L, cores, seed=0)
+    t0 = time.time()
+    O.full_walk(L, st[0], 64, trace=False)
+    per_step = (time.time() - t0) / 64
+    steps = int(max(64, min(32768, seconds_target / max(per_step, 1e-9))))
+    t0 = time.time()
+    res = O.full_walks(L, st, steps, n_threads=cores)
+    dt = time.time() - t0
+    total = int(res["steps_done"].sum())
+    return {"value": total / dt, "unit": "walk steps/s", "cores": cores, "kind": "oracle",
+            "sample": f"{cores} whole-space walks x {steps} moves at L={L} (seed 0 starts), "
+                      f"one walk per host thread, {dt:.1f} s wall"}
+
+
+FULL_WORKLOAD = dict(L=128, n_walks=65536, walk_len=32768)
+
+
+def calibration_copy(mib: int):
+    """A plain device copy of known size, run for the HBM-counter scale."""
+    import torch
+    if mib:
+        src_t = torch.ones(mib << 20, dtype=torch.uint8, device="cuda")
+        dst_t = torch.empty_like(src_t)
+        dst_t.copy_(src_t)
+        torch.cuda.synchronize()
+        del src_t, dst_t
+
+
+def run_full(L: int, n: int, walk_len: int, steps: int, warmup: int, cpu: bool, calib_mib: int = 0):
+    """Whole-space walks (labs_full_walks): walk steps/s, neighbour evals/s
+    (L per move) and the INT32 VALU roofline of the whole-space kernel."""
+    import torch
+    from paper_2210_15962_amd import labs
+    plan = labs.make_plan()
+    ws = labs.alloc_workspace(labs.full_workspace_bytes(L, n, walk_len, plan))
+    calibration_copy(calib_mib)
+    for w in range(warmup):
+        labs.full_walks(L, n, walk_len, seed=1000 + w, plan=plan, workspace=ws)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    kernel_ms, results = 0.0, []
+    t0 = time.perf_counter()
+    for s in range(steps):
+        ev0.record(stream)
+        res = labs.full_walks(L, n, walk_len, seed=s, plan=plan, workspace=ws, cap_steps=True)
+        ev1.record(stream)
+        ev1.synchronize()
+        kernel_ms += ev0.elapsed_time(ev1)
+        results.append((res["steps_done"], res["cap_steps"]))
+    wall = time.perf_counter() - t0
+    del ws
+    torch.cuda.empty_cache()
+    total = int(sum(int(r[0].sum().item()) for r in results))
+    cap_scans = [int(sum(int(r[1][:, k].sum().item()) for r in results)) for k in range(4)]
+    alg_ops = sum(c * full_ops_per_scan(L, cap) for c, cap in zip(cap_scans, CAPS))
+    avg_launch_s = kernel_ms / 1e3 / steps
+    achieved = alg_ops / steps / avg_launch_s
+    nw = (L - 1 + 31) // 32
+    tag = f"full_walk_kernel<NW={nw}>@{kernel_source_tag('labs_full.hip')}"
+    sps = total / wall
+    out = {"metric": "whole-space walk steps/s", "value": sps, "unit": "walk steps/s",
+           "steps": steps, "warmup": warmup, "ms_per_step": wall * 1e3 / steps, "dtype": "int32",
+           "data": "synthetic",
+           "config": {"workload": f"whole-space LABS self-avoiding walks, L={L}, {n} walks x "
+                                  f"{walk_len} moves, seeded uniform starts",
+                      "L": L, "n_walks": n, "walk_len": walk_len, "lanes_per_walk": 4},
+           "neighbour_evals_per_s": sps * L,
+           "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": INT32_VALU_PEAK / 1e12,
+                        "unit": "TOP/s", "frac": achieved / INT32_VALU_PEAK,
+                        "traffic": load_counter_traffic(tag, f"full_walk_kernel_L{L}_traffic.json"),
+                        "kernel": tag, "avg_launch_ms": avg_launch_s * 1e3,
+                        "alg_ops_per_launch": alg_ops / steps,
+                        "ops_per_neighbour_eval": alg_ops / max(sum(cap_scans) * L, 1),
+                        "scans_by_plane_cap": {str(c or "all"): v for c, v in zip(CAPS, cap_scans)}}}
+    if cpu:
+        out["cpu_baseline"] = cpu_baseline_full(L)
+    return out
 
 
 def serve_workload(n_req: int, rate: float, seed: int = 0):
@@ -312,6 +421,10 @@ def main():
     ap.add_argument("--solve-time-limit", type=float, default=600.0)
     ap.add_argument("--solve-walks", type=int, default=262144)
     ap.add_argument("--solve-seeds", type=str, default="0")
+    ap.add_argument("--full", type=int, default=0,
+                    help="whole-space walks at this L only (65,536 walks x 32,768 moves by default)")
+    ap.add_argument("--full-walks", type=int, default=FULL_WORKLOAD["n_walks"])
+    ap.add_argument("--full-walk-len", type=int, default=FULL_WORKLOAD["walk_len"])
     ap.add_argument("--paper-regime", type=str, default="",
                     help="comma-separated L: rounds of fresh 8D-move walks (Sec. 4) only")
     ap.add_argument("--paper-walks", type=int, default=262144)
@@ -332,6 +445,12 @@ def main():
         for sd in [int(x) for x in args.solve_seeds.split(",")]:
             print(json.dumps(run_solve_target(int(Ls), int(Es), args.solve_time_limit, args.solve_walks, sd)),
                   flush=True)
+        return
+
+    if args.full:
+        print(json.dumps(run_full(args.full, args.full_walks, args.full_walk_len, args.steps,
+                                  args.warmup, not args.no_cpu_baseline, args.calibration_copy_mib)),
+              flush=True)
         return
 
     if args.paper_regime:
@@ -361,13 +480,7 @@ def main():
     launches = (n + conc - 1) // conc
     ws = labs.alloc_workspace(labs.workspace_bytes(L, n, walk_len, plan))
     stream = torch.cuda.current_stream()
-    if args.calibration_copy_mib:
-        nb = args.calibration_copy_mib << 20
-        src_t = torch.ones(nb, dtype=torch.uint8, device="cuda")
-        dst_t = torch.empty_like(src_t)
-        dst_t.copy_(src_t)
-        torch.cuda.synchronize()
-        del src_t, dst_t
+    calibration_copy(args.calibration_copy_mib)
 
     def one_step(seed):
         return labs.walks(L, n, walk_len, seed=seed, plan=plan, workspace=ws, cap_steps=True)
