@@ -104,3 +104,43 @@ def test_cap_counts_cover_every_scan():
     caps = res["cap_steps"].cpu().numpy().astype(np.int64)
     np.testing.assert_array_equal(caps.sum(axis=1), res["steps_done"].cpu().numpy()
                                   + (res["steps_done"].cpu().numpy() < walk_len))
+
+
+def _unpack_full(keys, L):
+    """int8 +-1 sequences [n, L] from packed whole-space keys (bit i-1 = s_i)."""
+    bits = np.unpackbits(np.ascontiguousarray(keys).view(np.uint8).reshape(len(keys), -1),
+                         axis=1, bitorder="little")[:, :L]
+    return (1 - 2 * bits.astype(np.int8)).astype(np.int8)
+
+
+def test_bench_workload_L128_65536_walks_32768_moves():
+    """The whole-space bench configuration (bench.py --full 128): E of every
+    best sequence recomputed by the energy kernel, E = floor(L/2) (mod 4), and
+    trace prefixes plus prefix-length runs of sampled walks against the oracle."""
+    labs = _labs()
+    L, n, steps = 128, 65536, 32768
+    plan = labs.make_plan()
+    ws = labs.alloc_workspace(labs.full_workspace_bytes(L, n, steps, plan))
+    res = labs.full_walks(L, n, steps, seed=0, plan=plan, workspace=ws, n_trace=2)
+    torch.cuda.synchronize()
+    del ws
+    torch.cuda.empty_cache()
+    best = _u64(res["best_seq"]).reshape(n, -1)
+    E_best = res["best_E"].cpu().numpy()
+    s = _unpack_full(best, L)
+    E = np.concatenate([labs.energy(torch.from_numpy(s[i:i + 16384]).cuda()).cpu().numpy()
+                        for i in range(0, n, 16384)])
+    np.testing.assert_array_equal(E, E_best)
+    assert ((E_best - L // 2) % 4 == 0).all() and (E_best >= L // 2).all()
+    assert (res["steps_done"].cpu().numpy() <= steps).all()
+    keys = O.full_starts(L, n, 0)
+    prefix = 1500
+    for i in range(2):
+        r = O.full_walk(L, keys[i], prefix)
+        np.testing.assert_array_equal(res["trace_j"][i].cpu().numpy()[: r.steps], r.trace_j)
+        np.testing.assert_array_equal(res["trace_E"][i].cpu().numpy()[: r.steps], r.trace_E)
+    idx = I.sample_indices(n, 4, 4, seed=5)
+    st = torch.from_numpy(I.as_int64_keys(keys[idx])).cuda()
+    short = labs.full_walks(L, len(idx), prefix, starts_t=st, plan=plan)
+    torch.cuda.synchronize()
+    _compare(L, keys[idx], short, prefix)
