@@ -599,10 +599,10 @@ __global__ void __launch_bounds__(kBlock) full_walk_kernel(const WalkLaunch a) {
       //     head when its status is still unknown.
       const uint32_t head = tk[0];
       const bool head_valid = !done && !lane_empty && npop < K && head != kKeyMax;
-      auto probe_head = [&]() {
+      auto probe_head = [&](uint32_t hk) {
         if (!pstarted) {
-          pkey = flip_key(P, head & 0xFFu);
-          pbucket = bucket_of_hash(hP ^ zob[head & 0xFFu], a.n_buckets);
+          pkey = flip_key(P, hk & 0xFFu);
+          pbucket = bucket_of_hash(hP ^ zob[hk & 0xFFu], a.n_buckets);
           pstarted = true;
         }
         uint32_t fs = 0;
@@ -616,14 +616,29 @@ __global__ void __launch_bounds__(kBlock) full_walk_kernel(const WalkLaunch a) {
           pbucket = (pbucket + 1u == a.n_buckets) ? 0u : pbucket + 1u;
         }
       };
-      if (head_valid && hstat == 0 && eager) probe_head();
+      if (head_valid && hstat == 0 && eager) probe_head(head);
       eager = false;
+      // Every head already known to be visited leaves its list now (a visited
+      // neighbour is never chosen), so the merge sees only heads that are new
+      // or not yet probed: a walk needs another round only when the group's
+      // best remaining head has not been probed.
+      if (head_valid && hstat == 2) {
+        ex |= 1ull << ((head & 0xFFu) / G);
+#pragma unroll
+        for (int q = 0; q + 1 < K; ++q) tk[q] = tk[q + 1];
+        tk[K - 1] = kKeyMax;
+        ++npop;
+        hstat = 0;
+        pstarted = false;
+      }
+      const uint32_t cur = tk[0];
+      const bool cur_valid = !done && !lane_empty && npop < K && cur != kKeyMax;
       // (3) merge the heads of the group.
-      const uint32_t my = head_valid ? head : kKeyMax;
+      const uint32_t my = cur_valid ? cur : kKeyMax;
       const uint32_t gmin = group_min<G>(my);
-      const bool owner = head_valid && my == gmin;
+      const bool owner = cur_valid && my == gmin;
       if (__ballot(owner && hstat == 0) != 0ull) {
-        if (owner && hstat == 0) probe_head();
+        if (owner && hstat == 0) probe_head(cur);
       }
       const uint32_t ostat = group_max<G>(owner ? (uint32_t)(hstat + 1) : 0u);
       const bool exhausted_any = group_max<G>((!done && !lane_empty && npop >= K) ? 1u : 0u) != 0u;
@@ -638,7 +653,7 @@ __global__ void __launch_bounds__(kBlock) full_walk_kernel(const WalkLaunch a) {
           win = gmin;
         } else if (ostat == 3u) {
           if (owner) {
-            ex |= 1ull << ((head & 0xFFu) / G);
+            ex |= 1ull << ((cur & 0xFFu) / G);
 #pragma unroll
             for (int q = 0; q + 1 < K; ++q) tk[q] = tk[q + 1];
             tk[K - 1] = kKeyMax;

@@ -760,10 +760,10 @@ __device__ __forceinline__ void run_block(const BlockTask &a, uint8_t *lds) {
       //     best head was probed earlier costs no memory access.
       const uint32_t head = tk[0];
       const bool head_valid = !done && !lane_empty && npop < K && head != kKeyMax;
-      auto probe_head = [&]() {
+      auto probe_head = [&](uint32_t hk) {
         if (!pstarted) {
-          pkey = flip_key(P, head & 0xFFu);
-          pbucket = bucket_of_hash(hP ^ zob[head & 0xFFu], a.n_buckets);
+          pkey = flip_key(P, hk & 0xFFu);
+          pbucket = bucket_of_hash(hP ^ zob[hk & 0xFFu], a.n_buckets);
           pstarted = true;
         }
         uint32_t slot = 0;
@@ -777,14 +777,29 @@ __device__ __forceinline__ void run_block(const BlockTask &a, uint8_t *lds) {
           pbucket = (pbucket + 1u == a.n_buckets) ? 0u : pbucket + 1u;
         }
       };
-      if (head_valid && hstat == 0 && eager) probe_head();
+      if (head_valid && hstat == 0 && eager) probe_head(head);
       eager = false;
+      // Every head already known to be visited leaves its list now (a visited
+      // neighbour is never chosen), so the merge sees only heads that are new
+      // or not yet probed: a walk needs another round only when the group's
+      // best remaining head has not been probed.
+      if (head_valid && hstat == 2) {
+        exclude((head & 0xFFu) / Gl);
+#pragma unroll
+        for (int q = 0; q + 1 < K; ++q) tk[q] = tk[q + 1];
+        tk[K - 1] = kKeyMax;
+        ++npop;
+        hstat = 0;
+        pstarted = false;
+      }
+      const uint32_t cur = tk[0];
+      const bool cur_valid = !done && !lane_empty && npop < K && cur != kKeyMax;
       // (3) merge the heads of the group.
-      const uint32_t my = head_valid ? head : kKeyMax;
+      const uint32_t my = cur_valid ? cur : kKeyMax;
       const uint32_t gmin = grp_min<G>(my, Gl);
-      const bool owner = head_valid && my == gmin;
+      const bool owner = cur_valid && my == gmin;
       if (__ballot(owner && hstat == 0) != 0ull) {
-        if (owner && hstat == 0) probe_head();
+        if (owner && hstat == 0) probe_head(cur);
       }
       const uint32_t ostat = grp_max<G>(owner ? (uint32_t)(hstat + 1) : 0u, Gl);
       const bool exhausted_any = grp_max<G>((!done && !lane_empty && npop >= K) ? 1u : 0u, Gl) != 0u;
@@ -799,7 +814,7 @@ __device__ __forceinline__ void run_block(const BlockTask &a, uint8_t *lds) {
           win = gmin;
         } else if (ostat == 3u) {
           if (owner) {
-            exclude((head & 0xFFu) / Gl);
+            exclude((cur & 0xFFu) / Gl);
 #pragma unroll
             for (int i = 0; i + 1 < K; ++i) tk[i] = tk[i + 1];
             tk[K - 1] = kKeyMax;
