@@ -348,6 +348,12 @@ int32_t labs_serve_stats(labs_server *server, labs_serve_counters *stats);
  *   target_E        : stop as soon as the best energy is <= target_E; 0 = none.
  *   max_rounds      : 0 = unlimited (then one of the limits above must be set).
  *   plan            : as for labs_walks (NULL fields = defaults).
+ *   first_round     : index of this call's first round (>= 0; 0 for a fresh
+ *                     run).  Rounds are deterministic in (seed, round), so a
+ *                     run stopped after r rounds resumes with first_round = r:
+ *                     taking the lower best_E of the two calls (the earlier
+ *                     call's on ties) and summing NFEs and walk steps gives
+ *                     the results of one uninterrupted run.
  * Results: best_E, best_seq (W words, packed as labs_walks), rounds run,
  * NFEs, walk steps made, seconds elapsed, and the time and NFEs at which
  * target_E was first reached (reached_target = 1), else -1.
@@ -366,6 +372,7 @@ typedef struct labs_solve_cfg {
   int32_t pad;
   int64_t max_rounds;
   labs_plan plan;
+  int64_t first_round;
 } labs_solve_cfg;
 
 typedef struct labs_solve_result {

@@ -34,6 +34,7 @@ int32_t layout(int32_t L, const labs_solve_cfg *c, SolveLayout &o) {
   if (c->walk_len < 0) return lsaw::set_error(LABS_EINVAL, "walk_len must be >= 0");
   if (c->time_limit_s < 0 || c->nses_limit < 0 || c->max_rounds < 0 || c->target_E < 0)
     return lsaw::set_error(LABS_EINVAL, "negative stopping limit");
+  if (c->first_round < 0) return lsaw::set_error(LABS_EINVAL, "first_round must be >= 0");
   if (!(c->time_limit_s > 0 || c->nses_limit > 0 || c->max_rounds > 0 || c->target_E > 0))
     return lsaw::set_error(LABS_EINVAL, "no stopping condition (time, NSEs, target or rounds)");
   const int D = lsaw::free_bits(L);
@@ -99,8 +100,9 @@ int32_t labs_solve(int32_t L, const labs_solve_cfg *cfg, void *workspace, uint64
     if (cfg->time_limit_s > 0 && elapsed_s(t0) >= cfg->time_limit_s) break;
     if (cfg->nses_limit > 0 && res->nfes >= cfg->nses_limit) break;
     if (res->reached_target) break;
-    // walks r*n .. r*n + n - 1 of the seed's start stream
-    const uint64_t seed_r = cfg->seed + kGamma * ((uint64_t)r * (uint64_t)o.n * (uint64_t)o.W);
+    // walks q*n .. q*n + n - 1 of the seed's start stream, q = first_round + r
+    const uint64_t q = (uint64_t)cfg->first_round + (uint64_t)r;
+    const uint64_t seed_r = cfg->seed + kGamma * (q * (uint64_t)o.n * (uint64_t)o.W);
     rc = labs_walks(nullptr, L, o.n, o.walk_len, seed_r, &out, ws, o.tables, &cfg->plan, stream);
     if (rc != LABS_OK) return rc;
     hipError_t e = hipMemcpyAsync(hE.data(), dE, hE.size() * 4, hipMemcpyDeviceToHost, st);

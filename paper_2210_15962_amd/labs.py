@@ -54,7 +54,8 @@ class Instance(ctypes.Structure):
 class SolveCfg(ctypes.Structure):
     _fields_ = [("walks_per_round", I64), ("walk_len", I64), ("seed", U64),
                 ("time_limit_s", ctypes.c_double), ("nses_limit", ctypes.c_double),
-                ("target_E", I32), ("pad", I32), ("max_rounds", I64), ("plan", Plan)]
+                ("target_E", I32), ("pad", I32), ("max_rounds", I64), ("plan", Plan),
+                ("first_round", I64)]
 
 
 class SolveResult(ctypes.Structure):
@@ -455,6 +456,30 @@ def tune_get(L: int):
     return int(g.value), float(lf.value), rc == LABS_OK
 
 
+def save_tuning(path: str):
+    """Write the per-L tuning table (every odd L with an entry) as JSON:
+    {"L": {"lanes_per_walk": G, "load_factor": a}}."""
+    import json
+    table = {}
+    for L in range(3, l_max() + 1, 2):
+        g, lf, found = tune_get(L)
+        if found:
+            table[str(L)] = {"lanes_per_walk": g, "load_factor": lf}
+    with open(path, "w") as f:
+        json.dump(table, f, indent=1, sort_keys=True)
+    return table
+
+
+def load_tuning(path: str) -> int:
+    """Enter every entry of a JSON table written by save_tuning; returns the count."""
+    import json
+    with open(path) as f:
+        table = json.load(f)
+    for L, e in table.items():
+        tune_set(int(L), int(e["lanes_per_walk"]), float(e["load_factor"]))
+    return len(table)
+
+
 def autotune(L: int, n_walks: int = 131072, walk_len: int = 512, stream=None, device="cuda"):
     """Time lanes per walk / load factor for L on a short run; stores and returns the best.
 
@@ -545,11 +570,14 @@ class Server:
 # ------------------------------------------------------ solver and stopping model
 def solve(L: int, walks_per_round: int, walk_len: int = 0, seed: int = 0, time_limit_s: float = 0.0,
           nses_limit: float = 0.0, target_E: int = 0, max_rounds: int = 0,
-          plan: Optional[Plan] = None, workspace=None, stream=None, device="cuda") -> dict:
+          plan: Optional[Plan] = None, workspace=None, stream=None, device="cuda",
+          first_round: int = 0) -> dict:
     """Alg. 1: rounds of walks_per_round fresh walks until a stopping condition
-    holds (labs_solve).  walk_len 0 = 8 D.  Returns the global best and counts."""
+    holds (labs_solve).  walk_len 0 = 8 D.  first_round > 0 resumes a run that
+    stopped after that many rounds.  Returns the global best and counts."""
     cfg = SolveCfg(walks_per_round, walk_len, seed & 0xFFFFFFFFFFFFFFFF, time_limit_s, nses_limit,
-                   target_E, 0, max_rounds, plan if plan is not None else Plan(0, 0.0, 0))
+                   target_E, 0, max_rounds, plan if plan is not None else Plan(0, 0.0, 0),
+                   first_round)
     if workspace is None:
         nb = U64(0)
         _check(lib().labs_solve_workspace_bytes(L, ctypes.byref(cfg), ctypes.byref(nb)))

@@ -203,8 +203,24 @@ def test_solve_validation_before_any_launch():
     res = labs.SolveResult()
     assert lib.labs_solve(27, ctypes.byref(cfg), None, nb.value, None, ctypes.byref(res)) == labs.LABS_EINVAL
     assert lib.labs_solve(27, ctypes.byref(cfg), ctypes.c_void_p(1), 16, None, ctypes.byref(res)) == labs.LABS_EINVAL
+    cfg.first_round = -1
+    assert lib.labs_solve_workspace_bytes(27, ctypes.byref(cfg), ctypes.byref(nb)) == labs.LABS_EINVAL
+    cfg.first_round = 5
+    assert lib.labs_solve_workspace_bytes(27, ctypes.byref(cfg), ctypes.byref(nb)) == labs.LABS_OK
     cfg.walks_per_round = 0
     assert lib.labs_solve(27, ctypes.byref(cfg), ctypes.c_void_p(1), 1 << 40, None, ctypes.byref(res)) == labs.LABS_EINVAL
+
+
+def test_tuning_table_json_roundtrip(tmp_path):
+    labs.tune_set(201, 2, 0.6)
+    labs.tune_set(203, 8, 0.4)
+    path = str(tmp_path / "tune.json")
+    table = labs.save_tuning(path)
+    assert table["201"] == {"lanes_per_walk": 2, "load_factor": 0.6}
+    labs.tune_set(201, 4, 0.5)
+    labs.tune_set(203, 4, 0.5)
+    assert labs.load_tuning(path) == len(table)
+    assert labs.tune_get(201) == (2, 0.6, True) and labs.tune_get(203) == (8, 0.4, True)
 
 
 def test_full_space_sizes_and_validation_before_any_launch():

@@ -55,3 +55,22 @@ def test_time_limit_stops_the_run():
     r = labs.solve(101, 1024, time_limit_s=0.5, seed=3)
     assert r["rounds"] >= 1 and r["seconds"] >= 0.5
     assert r["seconds"] < 5.0
+
+
+def test_resumed_run_equals_uninterrupted_run():
+    """Rounds are deterministic in (seed, round): two rounds, then two more
+    from first_round = 2, give the best of four uninterrupted rounds."""
+    labs = _labs()
+    L, n, seed = 71, 256, 5
+    full = labs.solve(L, n, max_rounds=4, seed=seed)
+    a = labs.solve(L, n, max_rounds=2, seed=seed)
+    b = labs.solve(L, n, max_rounds=2, seed=seed, first_round=2)
+    best = a if a["best_E"] <= b["best_E"] else b
+    assert full["best_E"] == best["best_E"]
+    np.testing.assert_array_equal(full["best_seq"], best["best_seq"])
+    assert full["nfes"] == a["nfes"] + b["nfes"]
+    assert full["walk_steps"] == a["walk_steps"] + b["walk_steps"]
+    # and the resumed rounds are the oracle's walks 2n .. 4n - 1
+    D = (L + 1) // 2
+    ref = O.walks(L, O.starts(L, 4 * n, seed)[2 * n:], 8 * D)
+    assert b["best_E"] == int(ref["best_E"].min())
