@@ -450,7 +450,6 @@ __global__ void __launch_bounds__(kBlock) full_walk_kernel(const WalkLaunch a) {
   uint64_t h = 0;
   int64_t steps = 0;
   uint32_t prev_im1 = 0xFFFFFFFFu;
-  bool trapped = false;
   uint8_t *table = tables + (uint64_t)(active ? slot : 0) * a.table_bytes;
 
   uint32_t hP = 0u;
@@ -671,7 +670,6 @@ __global__ void __launch_bounds__(kBlock) full_walk_kernel(const WalkLaunch a) {
     if (active) {
       if (win == kKeyMax) {
         active = false;         // trapped walk stops here
-        trapped = true;
       } else {
         const uint32_t im1 = win & 0xFFu;
         const int32_t dE = 4 * ((int32_t)(win >> 8) - kBias);
@@ -722,7 +720,6 @@ __global__ void __launch_bounds__(kBlock) full_walk_kernel(const WalkLaunch a) {
     a.steps_done[walk] = steps;
     if (a.digest) a.digest[walk] = mix64(h ^ (uint64_t)steps);
   }
-  (void)trapped;
 }
 
 template <int NW>
