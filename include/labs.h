@@ -24,6 +24,9 @@
  *   W = ceil(D/64) uint64 words, row-major per sequence.  Free bit x_j (which
  *   is sequence element s_j) is bit (j-1)%64 of word (j-1)/64; a set bit means
  *   -1.  Bits above D must be zero.
+ * Whole search space (labs_full_*): any L with 3 <= L <= labs_full_l_max();
+ *   the whole sequence is packed the same way, bit i-1 = s_i, in
+ *   ceil(L/64) words, bits at L and above zero.
  */
 #ifndef LABS_H
 #define LABS_H
