@@ -4,7 +4,10 @@ A step is one pass of the whole hot path over one batch of synthetic input:
 labs_walks over the headline workload (L = 151, 65,536 walks of 131,072 moves
 from seeded uniform starts).  Prints one JSON line with walk steps/s (Sum of
 steps_done over the timed steps / time), neighbour evaluations/s, the INT32
-VALU roofline of the walk kernel and the CPU oracle baseline.
+VALU roofline of the walk kernel, the served stream (p50/p99 latency and
+served vs plain-batch steps/s at 10 and 200 req/s) and the CPU oracle baseline.
+Other workloads run alone under their flags (--full, --paper-regime,
+--mixed-batch, --serve-sweep, --solve-target).
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
 """
@@ -411,7 +414,8 @@ def main():
     ap.add_argument("--calibration-copy-mib", type=int, default=0,
                     help="run one plain device copy of this size first (counter calibration)")
     ap.add_argument("--serve-requests", type=int, default=64)
-    ap.add_argument("--serve-rate", type=float, default=10.0)
+    ap.add_argument("--serve-rates", type=str, default="10,200",
+                    help="arrival rates (req/s) of the serving legs in the default run")
     ap.add_argument("--serve-chunk", type=int, default=4096)
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--serve-sweep", type=str, default="",
@@ -548,8 +552,11 @@ def main():
     del ws
     torch.cuda.empty_cache()
     if not args.no_serve:
-        out["serving"] = run_serving(args.serve_requests, args.serve_rate, args.load_factor,
-                                     args.serve_chunk)
+        # both ends of the 10-200 req/s range: near capacity, and saturated
+        batch = run_plain_batch(args.serve_requests, args.load_factor)
+        out["serving"] = [run_serving(args.serve_requests, rate, args.load_factor, args.serve_chunk,
+                                      batch=batch)
+                          for rate in [float(x) for x in args.serve_rates.split(",")]]
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(L)
     print(json.dumps(out), flush=True)
