@@ -57,6 +57,14 @@ __device__ __forceinline__ uint32_t lshl_add(uint32_t a, uint32_t b) {
   return r;
 }
 
+// a * M + b on the 24-bit signed multiplier (one v_mad_i32_i24); |a| < 2^23.
+template <int M>
+__device__ __forceinline__ uint32_t mad_i24(uint32_t a, uint32_t b) {
+  uint32_t r;
+  asm("v_mad_i32_i24 %0, %1, %2, %3" : "=v"(r) : "v"(a), "i"(M), "v"(b));
+  return r;
+}
+
 __device__ __forceinline__ uint32_t funnel(uint32_t hi, uint32_t lo, uint32_t sh) {
   return __builtin_amdgcn_alignbit(hi, lo, sh);
 }

@@ -205,14 +205,18 @@ __device__ __forceinline__ uint32_t eval_key(const uint32_t *row, const uint8_t 
   });
   uint32_t H, kt;
   if constexpr (BP > 0) {
-    H = 0u - cnt[BM - 1];                        // sign plane: weight -2^(BP-1)
+    // sign plane: weight -2^(BP-1), so the Horner sum opens with
+    // cnt[BP-2] - 2 cnt[BP-1]
+    H = mad_i24<-2>(cnt[BM - 1], cnt[BM - 2]);
     kt = d1.z;                                   // nOdd << 8
+#pragma unroll
+    for (int b = BM - 3; b >= 0; --b) H = lshl_add<1>(H, cnt[b]);
   } else {
     H = cnt[BM - 1];                             // complemented sign planes
     kt = d1.y;                                   // (nOdd - 2 Kc) << 8
-  }
 #pragma unroll
-  for (int b = BM - 2; b >= 0; --b) H = lshl_add<1>(H, cnt[b]);
+    for (int b = BM - 2; b >= 0; --b) H = lshl_add<1>(H, cnt[b]);
+  }
   const uint32_t t = lshl_add<9>(H, kt);        // (sum_F+B sigma C) << 8
   const uint32_t kq = lshl_add<10>(q, d1.x);    // key constant + 4 (|MFB| - q) << 8
   // sg = ~0 when s_i = -1: kq - 1 + t; else kq + ~t = kq - 1 - t.
@@ -476,12 +480,16 @@ __global__ void __launch_bounds__(kBlock) full_walk_kernel(const WalkLaunch a) {
     });
   }
   auto sign_of = [&](int it) -> uint32_t {      // ~0 if s_i = -1, else 0 (it uniform)
-    uint32_t wv = 0u;
-    static_for<0, Gm::kSW>([&](auto wc) {
-      constexpr int w = decltype(wc)::value;
-      wv |= smk[w] & (0u - (uint32_t)((it >> 5) == w));
-    });
-    return (uint32_t)__builtin_amdgcn_sbfe((int)wv, it & 31, 1);
+    if constexpr (Gm::kSW == 1) {
+      return (uint32_t)__builtin_amdgcn_sbfe((int)smk[0], it & 31, 1);   // it < 32
+    } else {
+      uint32_t wv = 0u;
+      static_for<0, Gm::kSW>([&](auto wc) {
+        constexpr int w = decltype(wc)::value;
+        wv |= smk[w] & (0u - (uint32_t)((it >> 5) == w));
+      });
+      return (uint32_t)__builtin_amdgcn_sbfe((int)wv, it & 31, 1);
+    }
   };
   const int nruns = (int)__builtin_amdgcn_readfirstlane(runs[kRunSlots - 1]);
   constexpr uint64_t kMask = words_mask(NW, G);

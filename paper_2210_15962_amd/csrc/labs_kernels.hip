@@ -275,14 +275,18 @@ __device__ __forceinline__ uint32_t eval_key(const uint32_t *row, const uint8_t 
   uint32_t H;
   uint32_t nconst;
   if constexpr (BP > 0) {
-    H = 0u - cnt[BM - 1];                        // sign plane: weight -2^(BP-1)
+    // sign plane: weight -2^(BP-1), so the Horner sum opens with
+    // cnt[BP-2] - 2 cnt[BP-1]
+    H = mad_i24<-2>(cnt[BM - 1], cnt[BM - 2]);
     nconst = row[DS_N8];                         // N << 8
+#pragma unroll
+    for (int b = BM - 3; b >= 0; --b) H = lshl_add<1>(H, cnt[b]);
   } else {
     H = cnt[BM - 1];                             // complemented sign planes
     nconst = d1.w;                               // (N - 2 Kc) << 8
-  }
 #pragma unroll
-  for (int b = BM - 2; b >= 0; --b) H = lshl_add<1>(H, cnt[b]);
+    for (int b = BM - 2; b >= 0; --b) H = lshl_add<1>(H, cnt[b]);
+  }
   const uint32_t t = lshl_add<9>(H, nconst);    // (2 X + N) << 8
   const uint32_t kq = lshl_add<11>(q, d1.z);    // (((kc - 8 q) << 8) | (j - 1)) + 1
   // sg = ~0 when s_j = -1: kq - 1 + t; else kq + ~t = kq - 1 - t.
@@ -615,13 +619,17 @@ __device__ __forceinline__ void run_block(const BlockTask &a, uint8_t *lds) {
     });
   }
   auto sign_of = [&](int i) -> uint32_t {        // ~0 if s_j = -1, else 0 (i uniform)
-    // word select with masks (a select chain becomes a stack lookup table)
-    uint32_t wv = 0u;
-    static_for<0, kSW>([&](auto wc) {
-      constexpr int w = decltype(wc)::value;
-      wv |= smk[w] & (0u - (uint32_t)((i >> 5) == w));
-    });
-    return (uint32_t)__builtin_amdgcn_sbfe((int)wv, i & 31, 1);
+    if constexpr (kSW == 1) {
+      return (uint32_t)__builtin_amdgcn_sbfe((int)smk[0], i & 31, 1);   // i < 32
+    } else {
+      // word select with masks (a select chain becomes a stack lookup table)
+      uint32_t wv = 0u;
+      static_for<0, kSW>([&](auto wc) {
+        constexpr int w = decltype(wc)::value;
+        wv |= smk[w] & (0u - (uint32_t)((i >> 5) == w));
+      });
+      return (uint32_t)__builtin_amdgcn_sbfe((int)wv, i & 31, 1);
+    }
   };
   const int nruns = (int)__builtin_amdgcn_readfirstlane(runs[kRunSlots - 1]);
   constexpr uint64_t kMask = WordsMask<NW, G>::value;
