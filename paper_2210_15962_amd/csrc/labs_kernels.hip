@@ -215,7 +215,7 @@ __device__ __forceinline__ void load_candidate(const uint32_t *desc_row, const u
 // when the stored planes BP-1 and above of every lag word are copies of plane
 // BP-1; the caller checks that for every walk of the wave.  Then plane BP-1
 // is the sign plane of every word and enters with weight -2^(BP-1).
-template <int NW, int FW, int BW, int BP>
+template <int NW, int FW, int BW, int BP, bool kMadOpen = true>
 __device__ __forceinline__ uint32_t eval_key(const uint32_t *row, const uint8_t *lds,
                                              uint32_t colbase, const uint32_t *P, uint32_t sg) {
   using Gm = Geom<NW>;
@@ -274,13 +274,20 @@ __device__ __forceinline__ uint32_t eval_key(const uint32_t *row, const uint8_t 
   });
   uint32_t H;
   uint32_t nconst;
-  if constexpr (BP > 0) {
+  if constexpr (BP > 0 && kMadOpen) {
     // sign plane: weight -2^(BP-1), so the Horner sum opens with
     // cnt[BP-2] - 2 cnt[BP-1]
     H = mad_i24<-2>(cnt[BM - 1], cnt[BM - 2]);
     nconst = row[DS_N8];                         // N << 8
 #pragma unroll
     for (int b = BM - 3; b >= 0; --b) H = lshl_add<1>(H, cnt[b]);
+  } else if constexpr (BP > 0) {
+    // the same as a negation and shift-adds (the batch kernels' register
+    // allocation runs faster this way)
+    H = 0u - cnt[BM - 1];
+    nconst = row[DS_N8];
+#pragma unroll
+    for (int b = BM - 2; b >= 0; --b) H = lshl_add<1>(H, cnt[b]);
   } else {
     H = cnt[BM - 1];                             // complemented sign planes
     nconst = d1.w;                               // (N - 2 Kc) << 8
@@ -693,7 +700,7 @@ __device__ __forceinline__ void run_block(const BlockTask &a, uint8_t *lds) {
           for (int i = ib; i < ie; ++i) {
             // j > D reads a dead row whose key ~0 leaves the top-K unchanged
             const int j = r + 1 + Gl * i;
-            topk_insert<K>(tk, eval_key<NW, F, B, BPv>(desc + (j - 1) * Gm::DESC, cols, colbase, Pl,
+            topk_insert<K>(tk, eval_key<NW, F, B, BPv, (G > 0)>(desc + (j - 1) * Gm::DESC, cols, colbase, Pl,
                                                        sign_of(i)));
           }
         };
