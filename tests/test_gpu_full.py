@@ -113,12 +113,14 @@ def _unpack_full(keys, L):
     return (1 - 2 * bits.astype(np.int8)).astype(np.int8)
 
 
-def test_bench_workload_L128_65536_walks_32768_moves():
-    """The whole-space bench configuration (bench.py --full 128): E of every
+@pytest.mark.parametrize("L,steps,prefix", [(128, 32768, 1500), (64, 32768, 3000), (192, 16384, 600)])
+def test_bench_workload_65536_walks(L, steps, prefix):
+    """The whole-space bench configurations (bench.py --full L): E of every
     best sequence recomputed by the energy kernel, E = floor(L/2) (mod 4), and
     trace prefixes plus prefix-length runs of sampled walks against the oracle."""
     labs = _labs()
-    L, n, steps = 128, 65536, 32768
+    n = 65536
+    print(f"[full] L={L} n={n} steps={steps}", flush=True)
     plan = labs.make_plan()
     ws = labs.alloc_workspace(labs.full_workspace_bytes(L, n, steps, plan))
     res = labs.full_walks(L, n, steps, seed=0, plan=plan, workspace=ws, n_trace=2)
@@ -134,7 +136,6 @@ def test_bench_workload_L128_65536_walks_32768_moves():
     assert ((E_best - L // 2) % 4 == 0).all() and (E_best >= L // 2).all()
     assert (res["steps_done"].cpu().numpy() <= steps).all()
     keys = O.full_starts(L, n, 0)
-    prefix = 1500
     for i in range(2):
         r = O.full_walk(L, keys[i], prefix)
         np.testing.assert_array_equal(res["trace_j"][i].cpu().numpy()[: r.steps], r.trace_j)
