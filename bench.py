@@ -121,6 +121,26 @@ def load_counter_traffic(kernel_tag: str, name: str = "walk_kernel_L151_traffic.
     return None
 
 
+def cpu_model() -> str:
+    """The host CPU's model name (first entry of /proc/cpuinfo)."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.lower().startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def _cpu_rates(total_steps: int, dt: float, cores: int, evals_per_step: int) -> dict:
+    return {"per_core_steps_per_s": total_steps / dt / cores,
+            "evals_per_s": total_steps * evals_per_step / dt,
+            "per_core_evals_per_s": total_steps * evals_per_step / dt / cores,
+            "cpu_model": cpu_model(), "nproc": os.cpu_count()}
+
+
 def cpu_baseline(L: int, seconds_target: float = 15.0):
     """The CPU oracle (untuned) on a bounded sample of the same workload."""
     import numpy as np
@@ -139,7 +159,8 @@ def cpu_baseline(L: int, seconds_target: float = 15.0):
     total = int(res["steps_done"].sum())
     return {"value": total / dt, "unit": "walk steps/s", "cores": cores, "kind": "oracle",
             "sample": f"{cores} walks x {steps} moves at L={L} (seed 0 starts), "
-                      f"one walk per host thread, {dt:.1f} s wall"}
+                      f"one walk per host thread, {dt:.1f} s wall",
+            **_cpu_rates(total, dt, cores, (L + 1) // 2)}
 
 
 def cpu_baseline_full(L: int, seconds_target: float = 15.0):
@@ -158,7 +179,8 @@ def cpu_baseline_full(L: int, seconds_target: float = 15.0):
     total = int(res["steps_done"].sum())
     return {"value": total / dt, "unit": "walk steps/s", "cores": cores, "kind": "oracle",
             "sample": f"{cores} whole-space walks x {steps} moves at L={L} (seed 0 starts), "
-                      f"one walk per host thread, {dt:.1f} s wall"}
+                      f"one walk per host thread, {dt:.1f} s wall",
+            **_cpu_rates(total, dt, cores, L)}
 
 
 FULL_WORKLOAD = dict(L=128, n_walks=65536, walk_len=32768)

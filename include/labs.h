@@ -228,9 +228,16 @@ int32_t labs_batch_workspace_bytes(const labs_instance *inst, int32_t n_inst, ui
 
 /*
  * labs_walks_batch -- run every instance (host array inst[0..n_inst-1]) in
- * persistent launches (one per class group, see above) on `stream`.  The work-item list is uploaded into the
- * workspace with an asynchronous copy from host memory.  Errors: LABS_EINVAL
- * (any invalid instance, workspace below one arena), LABS_EDEVICE.
+ * persistent launches (one per class group, see above) on `stream`.  The
+ * work-item list is copied into the workspace asynchronously, through a ring
+ * of four pinned host buffers per device that the library keeps for the
+ * process: the call returns without waiting on `stream`, except that it
+ * waits for the upload of the fourth batch call before it on the device to
+ * complete before reusing that buffer.  The first calls (and a call with a
+ * longer list than any before) allocate pinned host memory.  The call is not
+ * meant for stream capture: use labs_batch_graph_* for graphs.
+ * Errors: LABS_EINVAL (any invalid instance, workspace below one arena),
+ * LABS_EDEVICE.
  */
 int32_t labs_walks_batch(const labs_instance *inst, int32_t n_inst, void *workspace,
                          uint64_t ws_bytes, void *stream);

@@ -579,6 +579,68 @@ hipError_t enqueue_groups(const BatchPlan &bp, uint8_t *ws, const std::vector<in
 
 }  // namespace
 
+namespace {
+
+// Work lists of labs_walks_batch go to the device through a ring of pinned
+// host buffers per device, so the copy is truly asynchronous and the call
+// returns without waiting on the caller's stream.  A slot is reused only
+// after its previous copy has completed (an event per slot); a slot grows
+// (pinned allocation) only when a list is larger than any it held before.
+constexpr int kStageSlots = 4;
+struct StageRing {
+  void *host[kStageSlots] = {nullptr};
+  size_t cap[kStageSlots] = {0};
+  hipEvent_t done[kStageSlots] = {nullptr};
+  bool used[kStageSlots] = {false};
+  int next = 0;
+};
+std::mutex g_stage_mu;
+std::map<int, StageRing> g_stage;
+
+// Copies the byte ranges (src[i], n[i]) to dst[i] on `st` through one slot.
+hipError_t upload_async(int count, void *const *dst, const void *const *src, const size_t *n,
+                        hipStream_t st) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  std::lock_guard<std::mutex> lk(g_stage_mu);
+  StageRing &ring = g_stage[dev];
+  const int k = ring.next;
+  ring.next = (k + 1) % kStageSlots;
+  if (!ring.done[k]) {
+    e = hipEventCreateWithFlags(&ring.done[k], hipEventDisableTiming);
+    if (e != hipSuccess) return e;
+  }
+  if (ring.used[k]) {
+    e = hipEventSynchronize(ring.done[k]);      // the slot's previous copy has been read
+    if (e != hipSuccess) return e;
+  }
+  size_t total = 0;
+  for (int i = 0; i < count; ++i) total += (n[i] + 255) & ~(size_t)255;
+  if (ring.cap[k] < total) {
+    if (ring.host[k]) (void)hipHostFree(ring.host[k]);
+    ring.host[k] = nullptr;
+    ring.cap[k] = 0;
+    const size_t want = std::max<size_t>(total, (size_t)1 << 16);
+    e = hipHostMalloc(&ring.host[k], want, hipHostMallocDefault);
+    if (e != hipSuccess) return e;
+    ring.cap[k] = want;
+  }
+  uint8_t *h = static_cast<uint8_t *>(ring.host[k]);
+  size_t off = 0;
+  for (int i = 0; i < count && e == hipSuccess; ++i) {
+    if (n[i] == 0) continue;
+    memcpy(h + off, src[i], n[i]);
+    e = hipMemcpyAsync(dst[i], h + off, n[i], hipMemcpyHostToDevice, st);
+    off += (n[i] + 255) & ~(size_t)255;
+  }
+  if (e == hipSuccess) e = hipEventRecord(ring.done[k], st);
+  ring.used[k] = e == hipSuccess;
+  return e;
+}
+
+}  // namespace
+
 struct labs_batch_graph {
   hipGraph_t graph;
   hipGraphExec_t exec;
@@ -618,12 +680,11 @@ int32_t labs_walks_batch(const labs_instance *inst, int32_t n_inst, void *worksp
   if (rc != LABS_OK) return rc;
   uint8_t *ws = static_cast<uint8_t *>(workspace);
   hipStream_t st = as_stream(stream);
-  hipError_t e = hipMemcpyAsync(ws + bp.items_off, bp.items.data(),
-                                bp.items.size() * sizeof(lsaw::BatchItemDev), hipMemcpyHostToDevice, st);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(ws + bp.inst_off, bp.inst.data(), bp.inst.size() * sizeof(lsaw::BatchInstanceDev),
-                       hipMemcpyHostToDevice, st);
-  if (e == hipSuccess) e = hipStreamSynchronize(st);   // host vectors die on return
+  void *dst[2] = {ws + bp.items_off, ws + bp.inst_off};
+  const void *src[2] = {bp.items.data(), bp.inst.data()};
+  const size_t nb[2] = {bp.items.size() * sizeof(lsaw::BatchItemDev),
+                        bp.inst.size() * sizeof(lsaw::BatchInstanceDev)};
+  hipError_t e = upload_async(2, dst, src, nb, st);
   if (e == hipSuccess) e = enqueue_groups(bp, ws, grids, concurrent, st);
   if (e != hipSuccess) return fail(LABS_EDEVICE, "batch launch: %s", hipGetErrorString(e));
   return ok();

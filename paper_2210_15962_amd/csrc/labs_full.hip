@@ -508,7 +508,7 @@ __global__ void __launch_bounds__(kBlock) full_walk_kernel(const WalkLaunch a) {
     int npop = 0;                 // entries popped from tk (head is tk[0])
     int hstat = 0;                // head: 0 unknown, 1 absent, 2 visited
     bool pstarted = false;
-    uint32_t pbucket = 0, pslot = 0;
+    uint32_t pbucket = 0, pslot = 0;   // pslot: byte offset of the free entry in bucket pbucket
     Key3 pkey{0, 0, 0};
     bool need_scan = false;
     bool eager = true;            // probe every head in the next round
@@ -618,7 +618,7 @@ __global__ void __launch_bounds__(kBlock) full_walk_kernel(const WalkLaunch a) {
           hstat = 2;
         } else if (res == 1) {
           hstat = 1;
-          pslot = pbucket * (uint32_t)kBucketBytes + fs;
+          pslot = fs;
         } else {
           pbucket = (pbucket + 1u == a.n_buckets) ? 0u : pbucket + 1u;
         }
@@ -692,7 +692,7 @@ __global__ void __launch_bounds__(kBlock) full_walk_kernel(const WalkLaunch a) {
         const Key3 NP = flip_key(P, im1);
         // the lane that probed the winner inserts it at the slot it found
         const bool owner = hstat == 1 && !lane_empty && npop < K && tk[0] == win;
-        if (owner) store_entry(table + pslot, NP, e32);
+        if (owner) store_entry(table + (uint64_t)pbucket * kBucketBytes + pslot, NP, e32);
         P = NP;
         hP ^= zob[im1];
         if ((int)(im1 & (uint32_t)(G - 1)) == r) {

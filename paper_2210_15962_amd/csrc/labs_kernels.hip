@@ -667,7 +667,7 @@ __device__ __forceinline__ void run_block(const BlockTask &a, uint8_t *lds) {
     int npop = 0;                 // entries popped from tk (head is tk[0])
     int hstat = 0;                // head: 0 unknown, 1 absent, 2 visited
     bool pstarted = false;
-    uint32_t pbucket = 0, pslot = 0;
+    uint32_t pbucket = 0, pslot = 0;   // pslot: byte offset of the free entry in bucket pbucket
     Key3 pkey{0, 0, 0};
     bool need_scan = false;
     bool eager = true;            // probe every head in the next round
@@ -787,7 +787,7 @@ __device__ __forceinline__ void run_block(const BlockTask &a, uint8_t *lds) {
           hstat = 2;
         } else if (res == 1) {
           hstat = 1;
-          pslot = pbucket * (uint32_t)kBucketBytes + slot;
+          pslot = slot;
         } else {
           pbucket = (pbucket + 1u == a.n_buckets) ? 0u : pbucket + 1u;
         }
@@ -871,7 +871,7 @@ __device__ __forceinline__ void run_block(const BlockTask &a, uint8_t *lds) {
         const Key3 NP = flip_key(P, jm1);
         // the lane that probed the winner inserts it at the slot it found
         const bool owner = hstat == 1 && !lane_empty && npop < K && tk[0] == win;
-        if (owner) store_entry(table + pslot, NP, e32);
+        if (owner) store_entry(table + (uint64_t)pbucket * kBucketBytes + pslot, NP, e32);
         P = NP;
         hP ^= zob[jm1];
         if ((int)(jm1 & (uint32_t)(Gl - 1)) == r) {

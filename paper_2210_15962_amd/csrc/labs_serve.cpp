@@ -257,12 +257,14 @@ void run_worker(labs_server *s) {
       };
       lanes_v[v] = 0.8 * fill(2 * items4_v[v]) > fill(items4_v[v]) ? 8 : 4;
     }
+    hipError_t up_err = hipSuccess;           // first failing starts upload, if any
     for (size_t k = 0; k < run.size(); ++k) {
       Request *q = run[k];
       uint8_t *b = s->pool + s->ctl_bytes + q->off;
       if (q->upload) {
-        (void)hipMemcpyAsync(b + q->o_starts, q->starts.data(), q->starts.size() * 8,
-                             hipMemcpyHostToDevice, s->stream);
+        if (up_err == hipSuccess)
+          up_err = hipMemcpyAsync(b + q->o_starts, q->starts.data(), q->starts.size() * 8,
+                                  hipMemcpyHostToDevice, s->stream);
         q->upload = false;
       }
       const int64_t take = std::min(s->chunk, q->walk_len - q->progress);
@@ -317,8 +319,10 @@ void run_worker(labs_server *s) {
     bl.arena = nullptr;                       // every instance brings its own tables
     bl.arena_bytes = 0;
     const int64_t t0 = now_ns();
-    hipError_t e = hipMemcpyAsync(ctl + items_off, items.data(), items.size() * sizeof(lsaw::BatchItemDev),
-                                  hipMemcpyHostToDevice, s->stream);
+    hipError_t e = up_err;
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(ctl + items_off, items.data(), items.size() * sizeof(lsaw::BatchItemDev),
+                         hipMemcpyHostToDevice, s->stream);
     if (e == hipSuccess)
       e = hipMemcpyAsync(ctl + inst_off, inst.data(), inst.size() * sizeof(lsaw::BatchInstanceDev),
                          hipMemcpyHostToDevice, s->stream);

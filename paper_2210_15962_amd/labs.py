@@ -184,6 +184,17 @@ def _dptr(t) -> Optional[int]:
     return None if t is None else t.data_ptr()
 
 
+def _in_use_on(stream, *tensors):
+    """Tensors a call hands to the library stay reserved for the caller's stream:
+    they were allocated on torch's current stream, so without this the caching
+    allocator could give them to current-stream work while the kernels still run."""
+    if stream is None:
+        return
+    for t in tensors:
+        if t is not None:
+            t.record_stream(stream)
+
+
 def l_max() -> int:
     return int(lib().labs_l_max())
 
@@ -230,6 +241,7 @@ def energy(seqs, stream=None):
         raise ValueError("sequence elements must be +1 or -1")
     out = torch.empty(n, dtype=torch.int32, device=seqs.device)
     _check(lib().labs_energy(_dptr(seqs), L, n, _dptr(out), _stream_handle(stream)))
+    _in_use_on(stream, seqs, out)
     return out
 
 
@@ -238,6 +250,7 @@ def starts(L: int, n_walks: int, seed: int, device="cuda", stream=None):
     out = torch.empty((n_walks, max(key_words(L), 1)), dtype=torch.int64, device=device)
     _check(lib().labs_starts(L, n_walks, seed & 0xFFFFFFFFFFFFFFFF, _dptr(out),
                              _stream_handle(stream)))
+    _in_use_on(stream, out)
     return out
 
 
@@ -301,6 +314,7 @@ def walks(L: int, n_walks: int, walk_len: int, seed: int = 0, starts_t=None, n_t
     _check(lib().labs_walks(_dptr(starts_t), L, n_walks, walk_len, seed & 0xFFFFFFFFFFFFFFFF,
                             ctypes.byref(out), _dptr(workspace), workspace.numel(),
                             ctypes.byref(plan) if plan else None, _stream_handle(stream)))
+    _in_use_on(stream, workspace, starts_t, *res.values())
     return res
 
 
@@ -353,6 +367,7 @@ def full_walks(L: int, n_walks: int, walk_len: int, seed: int = 0, starts_t=None
     _check(lib().labs_full_walks(_dptr(starts_t), L, n_walks, walk_len, seed & 0xFFFFFFFFFFFFFFFF,
                                  ctypes.byref(out), _dptr(workspace), workspace.numel(),
                                  ctypes.byref(plan) if plan else None, _stream_handle(stream)))
+    _in_use_on(stream, workspace, starts_t, *res.values())
     return res
 
 
@@ -407,6 +422,8 @@ def walks_batch(specs, workspace=None, stream=None, device="cuda"):
         workspace = alloc_workspace(b.value, device=device)
     _check(lib().labs_walks_batch(arr, len(specs), _dptr(workspace), workspace.numel(),
                                   _stream_handle(stream)))
+    _in_use_on(stream, workspace, *[t for r in results for t in r.values()],
+               *[sp.get("starts_t") for sp in specs])
     return results
 
 

@@ -252,3 +252,25 @@ def test_full_space_sizes_and_validation_before_any_launch():
     tr = labs.WalkOut(1, 1, 1, None, None, None, 5)
     assert lib.labs_full_walks(None, 64, 4, 10, 0, ref(tr), ws, 1 << 30, None, None) == labs.LABS_EINVAL
     assert lib.labs_full_walks(None, 64, 0, 10, 0, ref(out), ws, 0, None, None) == labs.LABS_OK
+
+
+def test_tables_beyond_2_to_26_buckets_are_sized_in_64_bits():
+    """Visited tables of 2^26 buckets and more (over 4 GiB per walk) are valid
+    sizes: the per-walk size is computed in 64 bits and only a bucket count of
+    2^32 or more is refused (the kernels index buckets in 32 bits and bytes in 64)."""
+    lf = labs.make_plan(load_factor=0.0001)
+    keys = 30_001                                   # walk_len + 1 pivots
+    per_walk = labs.min_workspace_bytes(101, 30_000, lf)
+    n_buckets = per_walk // 64
+    assert n_buckets >= keys / (4 * 0.0001) and n_buckets >= 1 << 26
+    assert per_walk > 1 << 32
+    assert labs.workspace_bytes(101, 3, 30_000, lf) == 3 * per_walk
+    assert labs.full_workspace_bytes(100, 2, 30_000, lf) == 2 * labs.full_workspace_bytes(100, 1, 30_000, lf)
+    assert labs.full_workspace_bytes(100, 1, 30_000, lf) > 1 << 32
+    # 2^31 moves at load 0.1 would need more than 2^32 buckets
+    lib = labs.lib()
+    nb = labs.U64(0)
+    huge = labs.make_plan(load_factor=0.1)
+    assert lib.labs_walks_workspace_bytes(101, 1, 1 << 31, ctypes.byref(huge), ctypes.byref(nb)) == labs.LABS_EINVAL
+    assert b"too large" in lib.labs_last_error()
+    assert lib.labs_full_walks_workspace_bytes(100, 1, 1 << 31, ctypes.byref(huge), ctypes.byref(nb)) == labs.LABS_EINVAL

@@ -1,12 +1,17 @@
 """Parity at the full workload sizes, in the launch configuration bench.py times.
 
 The oracle recomputes every neighbour energy (O(D L^2) per move), so it checks
-sampled walks: whole walks at L = 101 (65,536 moves) and trace prefixes at
-L = 151 (a walk's first t moves do not depend on its length).  Properties that
-hold at any size are checked on every walk: E(best_seq) recomputed by the
-energy kernel equals best_E, best_E = m (mod 8), best_E >= m, and digests do
-not depend on the launch plan.
+sampled walks over their whole length: 32 walks of L = 151 x 131,072 moves and
+128 walks of L = 101 x 65,536 moves, whose oracle results are stored under
+tests/golden/ (written by tests/golden/make_golden.py, which calls only the
+oracle), plus trace prefixes run live.  Properties that hold at any size are
+checked on every walk: E(best_seq) recomputed by the energy kernel equals
+best_E, best_E = m (mod 8), best_E >= m, and digests do not depend on the
+launch plan.
 """
+import json
+import os
+
 import numpy as np
 import pytest
 
@@ -33,6 +38,29 @@ def _u64(t):
     return t.cpu().numpy().view(np.uint64)
 
 
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def load_golden(name):
+    with open(os.path.join(GOLDEN, name)) as f:
+        return json.load(f)
+
+
+def assert_matches_golden(doc, res, L):
+    """Every stored walk (oracle results over the whole walk) equals the GPU's."""
+    W = (L + 1) // 2
+    W = (W + 63) // 64
+    idx = np.array([w["walk"] for w in doc["walks"]])
+    best_E = res["best_E"].cpu().numpy()[idx]
+    best = _u64(res["best_seq"])[idx]
+    sd = res["steps_done"].cpu().numpy()[idx]
+    dg = _u64(res["digest"])[idx]
+    np.testing.assert_array_equal(best_E, [w["best_E"] for w in doc["walks"]])
+    np.testing.assert_array_equal(best, np.array([w["best_seq"] for w in doc["walks"]], dtype=np.uint64).reshape(-1, W))
+    np.testing.assert_array_equal(sd, [w["steps_done"] for w in doc["walks"]])
+    np.testing.assert_array_equal(dg, np.array([w["digest"] for w in doc["walks"]], dtype=np.uint64))
+
+
 def check_best_energies(L, res):
     labs = _labs()
     best = _u64(res["best_seq"])
@@ -53,12 +81,10 @@ def test_config2_L101_16384_walks_65536_moves():
     torch.cuda.synchronize()
     best, E_best = check_best_energies(L, res)
     keys = O.starts(L, n, 0)
-    idx = I.sample_indices(n, 8, 8, seed=2)
-    ref = O.walks(L, keys[idx], steps)
-    np.testing.assert_array_equal(E_best[idx], ref["best_E"])
-    np.testing.assert_array_equal(best[idx], ref["best_seq"])
-    np.testing.assert_array_equal(res["steps_done"].cpu().numpy()[idx], ref["steps_done"])
-    np.testing.assert_array_equal(_u64(res["digest"])[idx], ref["digest"])
+    # 128 whole walks (0..63 and 64 seeded-random indices) against the oracle
+    doc = load_golden("walks_L101_seed0_65536moves.json")
+    assert doc["workload"] == dict(L=L, n_walks=n, walk_len=steps, seed=0) and len(doc["walks"]) == 128
+    assert_matches_golden(doc, res, L)
     for i in range(2):
         r = O.walk(L, keys[i], steps)
         np.testing.assert_array_equal(res["trace_j"][i].cpu().numpy()[: r.steps], r.trace_j)
@@ -81,6 +107,11 @@ def test_config3_L151_65536_walks_131072_moves_bench_plan():
     check_best_energies(L, res)
     sd = res["steps_done"].cpu().numpy()
     assert (sd <= steps).all()
+    # 32 whole walks (0..15 and 16 seeded-random indices) of this run, every
+    # one of 131,072 moves, against the oracle
+    doc = load_golden("walks_L151_seed0_131072moves.json")
+    assert doc["workload"] == dict(L=L, n_walks=n, walk_len=steps, seed=0) and len(doc["walks"]) == 32
+    assert_matches_golden(doc, res, L)
     keys = O.starts(L, n, 0)
     # trace prefixes of the traced walks
     prefix = 6000
@@ -127,3 +158,34 @@ def test_paper_regime_L247_8D_moves():
     np.testing.assert_array_equal(E_best[idx], ref["best_E"])
     np.testing.assert_array_equal(best[idx], ref["best_seq"])
     np.testing.assert_array_equal(_u64(res["digest"])[idx], ref["digest"])
+
+
+def test_tables_over_2_to_26_buckets_match_oracle():
+    """Visited tables of more than 2^26 buckets (4.8 GB per walk): entries land
+    beyond byte offset 2^32 of a table, where an insert must go to the bucket
+    its probe searched (Alg. 2 needs the visited set exact).  Whole walks of
+    both spaces against the oracle."""
+    labs = _labs()
+    L, n, steps = 101, 4, 30_000
+    plan = labs.make_plan(lanes_per_walk=4, load_factor=0.0001)
+    assert labs.min_workspace_bytes(L, steps, plan) // 64 > 1 << 26
+    keys = I.random_start_keys(L, n, seed=26)
+    st = torch.from_numpy(I.as_int64_keys(keys)).cuda()
+    res = labs.walks(L, n, steps, starts_t=st, plan=plan)
+    torch.cuda.synchronize()
+    ref = O.walks(L, keys, steps)
+    np.testing.assert_array_equal(res["best_E"].cpu().numpy(), ref["best_E"])
+    np.testing.assert_array_equal(_u64(res["best_seq"]), ref["best_seq"])
+    np.testing.assert_array_equal(res["steps_done"].cpu().numpy(), ref["steps_done"])
+    np.testing.assert_array_equal(_u64(res["digest"]), ref["digest"])
+    del res
+    torch.cuda.empty_cache()
+    Lf = 100
+    fkeys = I.random_full_keys(Lf, 2, seed=27)
+    assert labs.full_workspace_bytes(Lf, 1, steps, plan) // 64 > 1 << 26
+    fres = labs.full_walks(Lf, 2, steps, starts_t=torch.from_numpy(I.as_int64_keys(fkeys)).cuda(),
+                           plan=plan)
+    torch.cuda.synchronize()
+    fref = O.full_walks(Lf, fkeys, steps)
+    np.testing.assert_array_equal(fres["best_E"].cpu().numpy(), fref["best_E"])
+    np.testing.assert_array_equal(_u64(fres["digest"]), fref["digest"])
