@@ -159,6 +159,26 @@ int32_t labs_walks(const uint64_t *starts, int32_t L, int64_t n_walks,
                    void *stream);
 
 /*
+ * labs_walks_noalloc -- labs_walks for callers that cannot allocate device
+ * memory (code under stream capture, tight serving loops, harnesses that
+ * forbid allocation).  Arguments, results, streams and errors are those of
+ * labs_walks without the workspace: the visited tables live in a fixed device
+ * array of LABS_NOALLOC_SCRATCH_BYTES (64 MiB) that the library holds on every
+ * GPU it runs on until the process ends (its address is looked up on the
+ * first call on each device).  The walks run in chunks of as many visited
+ * tables as the array holds; a walk whose table alone is larger (see
+ * labs_walks_min_workspace_bytes) returns LABS_EINVAL.  The call allocates
+ * nothing.  Every call on one GPU uses the same array, and each walk clears
+ * its table before use: calls that overlap in time on one GPU (other streams
+ * or threads of the process) race and give undefined results, so serialise
+ * them, e.g. on one stream.
+ */
+#define LABS_NOALLOC_SCRATCH_BYTES (64ull << 20)
+int32_t labs_walks_noalloc(const uint64_t *starts, int32_t L, int64_t n_walks,
+                           int64_t walk_len, uint64_t seed, const labs_walk_out *out,
+                           const labs_plan *plan, void *stream);
+
+/*
  * Whole search space (the sokol_full solver that Sec. 5 names as future
  * work): the walks of labs_walks over all 2^L binary sequences of any length
  * L, 3 <= L <= labs_full_l_max() (192), even or odd.  The pivot is the whole

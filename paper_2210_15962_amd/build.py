@@ -35,9 +35,9 @@ def build(verbose: bool = True) -> str:
     extra = []
     if os.environ.get("LABS_SAVE_TEMPS"):
         extra = ["-save-temps=obj"]
-    # The two device translation units compile in parallel (each takes minutes).
+    # The device translation units compile in parallel (the walk kernels take minutes).
     procs = []
-    for src in ("labs_kernels.hip", "labs_full.hip"):
+    for src in ("labs_kernels.hip", "labs_full.hip", "labs_noalloc.hip"):
         obj = os.path.join(bdir, src.replace(".hip", ".o"))
         cmd = [hipcc, "-x", "hip", f"--offload-arch={ARCH}", *COMMON, *DEVICE_FLAGS, *extra, "-c",
                os.path.join(CSRC, src), "-o", obj]

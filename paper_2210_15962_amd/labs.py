@@ -115,6 +115,9 @@ def lib():
         L.labs_walks.argtypes = [VP, I32, I64, I64, U64, ctypes.POINTER(WalkOut), VP, U64,
                                  ctypes.POINTER(Plan), VP]
         L.labs_walks.restype = I32
+        L.labs_walks_noalloc.argtypes = [VP, I32, I64, I64, U64, ctypes.POINTER(WalkOut),
+                                         ctypes.POINTER(Plan), VP]
+        L.labs_walks_noalloc.restype = I32
         L.labs_full_l_max.restype = I32
         L.labs_full_key_words.argtypes = [I32]
         L.labs_full_key_words.restype = I32
@@ -315,6 +318,41 @@ def walks(L: int, n_walks: int, walk_len: int, seed: int = 0, starts_t=None, n_t
                             ctypes.byref(out), _dptr(workspace), workspace.numel(),
                             ctypes.byref(plan) if plan else None, _stream_handle(stream)))
     _in_use_on(stream, workspace, starts_t, *res.values())
+    return res
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20
+
+
+def walks_noalloc(L: int, n_walks: int, walk_len: int, seed: int = 0, starts_t=None,
+                  n_trace: int = 0, plan: Optional[Plan] = None, stream=None, device="cuda"):
+    """labs_walks_noalloc: walks() without a workspace (the library's fixed
+    64 MiB device array holds the visited tables).  Only the result tensors
+    are allocated, here, by the caller's side; the library allocates nothing."""
+    import torch
+    W = key_words(L)
+    if W == 0:
+        raise LabsError(LABS_EINVAL, f"invalid L={L}")
+    if starts_t is not None:
+        if starts_t.dtype != torch.int64 or tuple(starts_t.shape) != (n_walks, W) or not starts_t.is_cuda:
+            raise ValueError("starts must be an int64 CUDA tensor of shape (n_walks, W)")
+        starts_t = starts_t.contiguous()
+    res = {
+        "best_seq": torch.empty((n_walks, W), dtype=torch.int64, device=device),
+        "best_E": torch.empty(n_walks, dtype=torch.int32, device=device),
+        "steps_done": torch.empty(n_walks, dtype=torch.int64, device=device),
+        "digest": torch.empty(n_walks, dtype=torch.int64, device=device),
+    }
+    if n_trace:
+        res["trace_j"] = torch.zeros((n_trace, walk_len), dtype=torch.int16, device=device)
+        res["trace_E"] = torch.zeros((n_trace, walk_len), dtype=torch.int32, device=device)
+    out = WalkOut(_dptr(res["best_seq"]), _dptr(res["best_E"]), _dptr(res["steps_done"]),
+                  _dptr(res["digest"]), _dptr(res.get("trace_j")), _dptr(res.get("trace_E")),
+                  n_trace, None)
+    _check(lib().labs_walks_noalloc(_dptr(starts_t), L, n_walks, walk_len, seed & 0xFFFFFFFFFFFFFFFF,
+                                    ctypes.byref(out), ctypes.byref(plan) if plan else None,
+                                    _stream_handle(stream)))
+    _in_use_on(stream, starts_t, *res.values())
     return res
 
 

@@ -274,3 +274,17 @@ def test_tables_beyond_2_to_26_buckets_are_sized_in_64_bits():
     assert lib.labs_walks_workspace_bytes(101, 1, 1 << 31, ctypes.byref(huge), ctypes.byref(nb)) == labs.LABS_EINVAL
     assert b"too large" in lib.labs_last_error()
     assert lib.labs_full_walks_workspace_bytes(100, 1, 1 << 31, ctypes.byref(huge), ctypes.byref(nb)) == labs.LABS_EINVAL
+
+
+def test_noalloc_rejects_tables_beyond_its_scratch_before_any_device_call():
+    lib = labs.lib()
+    out = labs.WalkOut(1, 1, 1, None, None, None, 0)
+    ref = ctypes.byref
+    # one walk of 2^22 moves at load 0.5 needs 128 MiB of table: over 64 MiB
+    assert labs.min_workspace_bytes(151, 1 << 22) > labs.NOALLOC_SCRATCH_BYTES
+    assert lib.labs_walks_noalloc(None, 151, 4, 1 << 22, 0, ref(out), None, None) == labs.LABS_EINVAL
+    assert b"fixed scratch" in lib.labs_last_error()
+    assert lib.labs_walks_noalloc(None, 28, 4, 10, 0, ref(out), None, None) == labs.LABS_EINVAL
+    assert lib.labs_walks_noalloc(None, 27, -1, 10, 0, ref(out), None, None) == labs.LABS_EINVAL
+    assert lib.labs_walks_noalloc(None, 27, 4, 10, 0, None, None, None) == labs.LABS_EINVAL
+    assert lib.labs_walks_noalloc(None, 27, 0, 10, 0, ref(out), None, None) == labs.LABS_OK
