@@ -97,13 +97,29 @@ def test_batch_graph_replays_match_eager():
 
 
 def test_config4_256_instances_one_launch():
-    """256 instances, L uniform odd in [61, 223], 1024 walks x 32,768 moves."""
+    """256 instances, L uniform odd in [61, 223], 1024 walks x 32,768 moves.
+    Two whole walks of every instance, read from the batch output, against
+    the oracle (results stored by tests/golden/make_golden.py)."""
+    import json
+    import os
     labs = _labs()
     Ls = I.odd_lengths(256, 61, 223, seed=0)
     specs = [dict(L=int(L), n_walks=1024, walk_len=32768, seed=i) for i, L in enumerate(Ls)]
     g = labs.BatchGraph(specs)
     res = g.launch()
     torch.cuda.synchronize()
+    with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                           "batch_mixedL_61_223_32768moves.json")) as f:
+        doc = json.load(f)
+    assert len(doc["walks"]) == 512
+    for w in doc["walks"]:
+        r = res[w["inst"]]
+        assert specs[w["inst"]]["L"] == w["L"]
+        k = w["walk"]
+        assert r["best_E"][k].item() == w["best_E"], (w["inst"], k)
+        assert _u64(r["digest"])[k] == w["digest"], (w["inst"], k)
+        assert r["steps_done"][k].item() == w["steps_done"], (w["inst"], k)
+        np.testing.assert_array_equal(_u64(r["best_seq"])[k], np.array(w["best_seq"], dtype=np.uint64))
     for idx in I.sample_indices(256, 2, 3, seed=4):
         sp = dict(specs[idx])
         sp["lanes_per_walk"] = labs.tune_get(sp["L"])[0]
