@@ -99,13 +99,15 @@ typedef struct labs_walk_out {
   int16_t *trace_j;     /* [n_trace][walk_len] or NULL: flipped free bit j (1-based) */
   int32_t *trace_E;     /* [n_trace][walk_len] or NULL: energy after each move */
   int64_t n_trace;      /* traces are written for walks 0..n_trace-1 */
-  uint32_t *cap_steps;  /* [n_walks][4] or NULL (labs_walks only; batches and the
-                           server require NULL): neighbourhood scans of the walk
+  uint32_t *cap_steps;  /* [n_walks][4] or NULL: neighbourhood scans of the walk
                            evaluated on 4, 5 or 6 C planes, or on the stored
-                           per-word plane counts.  The low planes suffice whenever
-                           every c_t = (C_t - 1)/2 of the walks sharing a wavefront
-                           fits in that many bits; the counts let a caller price
-                           the evaluation work actually needed. */
+                           per-word plane counts (one scan per move, plus the
+                           last scan of a trapped walk).  The low planes suffice
+                           whenever every c_t = (C_t - 1)/2 of the walks sharing
+                           a wavefront fits in that many bits, so the counts
+                           depend on the launch plan: a performance record that
+                           lets a caller price the evaluation work actually
+                           needed, not a result. */
 } labs_walk_out;
 
 /*

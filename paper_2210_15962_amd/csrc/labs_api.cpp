@@ -386,8 +386,6 @@ int32_t plan_batch(const labs_instance *in, int32_t n_inst, BatchPlan &bp) {
     if (x.n_walks < 0) return fail(LABS_EINVAL, "instance %d: n_walks < 0", i);
     if (x.n_walks > 0 && (!x.out.best_seq || !x.out.best_E || !x.out.steps_done))
       return fail(LABS_EINVAL, "instance %d: best_seq, best_E and steps_done are required", i);
-    if (x.out.cap_steps)
-      return fail(LABS_EINVAL, "instance %d: cap_steps is reported by labs_walks only", i);
     if (x.out.n_trace < 0 || x.out.n_trace > x.n_walks)
       return fail(LABS_EINVAL, "instance %d: n_trace out of range", i);
     if (x.out.n_trace > 0 && (!x.out.trace_j || !x.out.trace_E))
@@ -398,6 +396,7 @@ int32_t plan_batch(const labs_instance *in, int32_t n_inst, BatchPlan &bp) {
     d.walk_len = x.walk_len;
     d.best_seq = x.out.best_seq;
     d.best_E = x.out.best_E;
+    d.cap_steps = x.out.cap_steps;
     d.steps_done = x.out.steps_done;
     d.digest = x.out.digest;
     d.trace_j = x.out.trace_j;

@@ -146,51 +146,120 @@ __device__ __forceinline__ uint32_t bucket_of_hash(uint32_t h, uint32_t n_bucket
   return __umulhi(h, n_buckets);
 }
 
-// Scan one bucket.  Returns 2 = key present, 1 = absent (slot = first free
-// entry), 0 = bucket full without the key.  Entries fill in order and are
-// never deleted, so a present key lies before the first free entry.  No
-// early exits: the four (or two) entries are tested with selects.
-__device__ __forceinline__ int scan_bucket(const uint8_t *bucket, const Key3 &k, bool e32,
-                                           uint32_t &slot) {
-  const uint4 *q = reinterpret_cast<const uint4 *>(bucket);
-  const uint4 v0 = q[0], v1 = q[1], v2 = q[2], v3 = q[3];
-  const uint32_t k0l = (uint32_t)k.w0, k0h = (uint32_t)(k.w0 >> 32);
-  const uint32_t k1l = (uint32_t)k.w1, k1h = (uint32_t)(k.w1 >> 32);
-  bool found;
-  uint32_t free_slot;
-  if (!e32) {
-    auto eq = [&](const uint4 &e) {
-      return e.x == k0l && e.y == k0h && e.z == k1l && e.w == (k1h | 0x80000000u);
-    };
-    found = eq(v0) || eq(v1) || eq(v2) || eq(v3);
-    free_slot = (v0.w >> 31) == 0u ? 0u : (v1.w >> 31) == 0u ? 16u :
-                (v2.w >> 31) == 0u ? 32u : (v3.w >> 31) == 0u ? 48u : 64u;
-  } else {
-    const uint32_t k2l = (uint32_t)k.w2, k2h = (uint32_t)(k.w2 >> 32);
-    auto eq = [&](const uint4 &lo, const uint4 &hi) {
-      return lo.x == k0l && lo.y == k0h && lo.z == k1l && lo.w == k1h && hi.x == k2l &&
-             hi.y == k2h && hi.z != 0u;
-    };
-    found = eq(v0, v1) || eq(v2, v3);
-    free_slot = v1.z == 0u ? 0u : v3.z == 0u ? 32u : 64u;
-  }
-  slot = free_slot;
-  return found ? 2 : (free_slot < 64u ? 1 : 0);
+// One bucket is one 128-byte line: a probe reads the whole line it fetches
+// from HBM.  Entry formats (keys of at most 95 / 127 / 191 bits):
+//   kE12: 10 entries of 12 bytes at dwords 3e..3e+2 (key bits 0-31, 32-63,
+//         64-94 with bit 31 of the third dword set when the entry is used);
+//         dword 31 holds the number of entries in the bucket;
+//   kE16: 8 entries of 16 bytes (key bits 0-126, bit 127 set when used);
+//   kE32: 4 entries of 32 bytes (key bits 0-191, dword 6 nonzero when used).
+// Entries fill in order and are never deleted, so a present key lies before
+// the first free entry.
+struct Bucket { uint4 q[8]; };
+
+__device__ __forceinline__ Bucket load_bucket(const uint8_t *bucket) {
+  const uint4 *p = reinterpret_cast<const uint4 *>(bucket);
+  Bucket b;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) b.q[i] = p[i];
+  return b;
 }
 
-__device__ __forceinline__ void store_entry(uint8_t *p, const Key3 &k, bool e32) {
-  if (!e32) {
-    uint4 v;
-    v.x = (uint32_t)k.w0; v.y = (uint32_t)(k.w0 >> 32);
-    v.z = (uint32_t)k.w1; v.w = (uint32_t)(k.w1 >> 32) | 0x80000000u;
-    *reinterpret_cast<uint4 *>(p) = v;
-  } else {
-    uint4 a, b;
-    a.x = (uint32_t)k.w0; a.y = (uint32_t)(k.w0 >> 32);
-    a.z = (uint32_t)k.w1; a.w = (uint32_t)(k.w1 >> 32);
-    b.x = (uint32_t)k.w2; b.y = (uint32_t)(k.w2 >> 32); b.z = 1u; b.w = 0u;
-    reinterpret_cast<uint4 *>(p)[0] = a;
-    reinterpret_cast<uint4 *>(p)[1] = b;
+// Dword i of a loaded bucket (i a compile-time constant after unrolling).
+__device__ __forceinline__ uint32_t bucket_dword(const Bucket &b, int i) {
+  const uint4 &v = b.q[i >> 2];
+  return (i & 3) == 0 ? v.x : (i & 3) == 1 ? v.y : (i & 3) == 2 ? v.z : v.w;
+}
+
+// Test one loaded bucket in format fmt, one of [FLO, FHI] (the formats the
+// caller's lengths can meet).  Returns 2 = key present, 1 = absent (n = index
+// of the first free entry), 0 = bucket full without the key.  No early exits:
+// every entry is compared.
+template <int FLO, int FHI>
+__device__ __forceinline__ int test_bucket(const Bucket &bk, const Key3 &k, int fmt, uint32_t &n) {
+  const uint32_t k0 = (uint32_t)k.w0, k1 = (uint32_t)(k.w0 >> 32);
+  const uint32_t k2 = (uint32_t)k.w1, k3 = (uint32_t)(k.w1 >> 32);
+  bool found = false;
+  uint32_t cnt = 0u, cap = 1u;
+  if constexpr (FLO <= kE12 && kE12 <= FHI) {
+    if (fmt == kE12) {
+      const uint32_t k2f = k2 | 0x80000000u;
+#pragma unroll
+      for (int e = 0; e < 10; ++e) {
+        const uint32_t x = (bucket_dword(bk, 3 * e) ^ k0) | (bucket_dword(bk, 3 * e + 1) ^ k1) |
+                           (bucket_dword(bk, 3 * e + 2) ^ k2f);
+        found = found || x == 0u;
+      }
+      cnt = bucket_dword(bk, 31);
+      cap = 10u;
+    }
+  }
+  if constexpr (FLO <= kE16 && kE16 <= FHI) {
+    if (fmt == kE16) {
+      const uint32_t k3f = k3 | 0x80000000u;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const uint32_t x = (bucket_dword(bk, 4 * e) ^ k0) | (bucket_dword(bk, 4 * e + 1) ^ k1) |
+                           (bucket_dword(bk, 4 * e + 2) ^ k2) | (bucket_dword(bk, 4 * e + 3) ^ k3f);
+        found = found || x == 0u;
+        cnt += bucket_dword(bk, 4 * e + 3) >> 31;
+      }
+      cap = 8u;
+    }
+  }
+  if constexpr (FLO <= kE32 && kE32 <= FHI) {
+    if (fmt == kE32) {
+      const uint32_t k4 = (uint32_t)k.w2, k5 = (uint32_t)(k.w2 >> 32);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const uint32_t used = bucket_dword(bk, 8 * e + 6);
+        const uint32_t x = (bucket_dword(bk, 8 * e) ^ k0) | (bucket_dword(bk, 8 * e + 1) ^ k1) |
+                           (bucket_dword(bk, 8 * e + 2) ^ k2) | (bucket_dword(bk, 8 * e + 3) ^ k3) |
+                           (bucket_dword(bk, 8 * e + 4) ^ k4) | (bucket_dword(bk, 8 * e + 5) ^ k5);
+        found = found || (x == 0u && used != 0u);
+        cnt += used != 0u ? 1u : 0u;
+      }
+      cap = 4u;
+    }
+  }
+  n = cnt;
+  return found ? 2 : (cnt < cap ? 1 : 0);
+}
+
+template <int FLO, int FHI>
+__device__ __forceinline__ int scan_bucket(const uint8_t *bucket, const Key3 &k, int fmt, uint32_t &n) {
+  return test_bucket<FLO, FHI>(load_bucket(bucket), k, fmt, n);
+}
+
+// Stores key k as entry n of a bucket (n = the first free entry found by its probe).
+template <int FLO, int FHI>
+__device__ __forceinline__ void store_entry(uint8_t *bucket, uint32_t n, const Key3 &k, int fmt) {
+  if constexpr (FLO <= kE12 && kE12 <= FHI) {
+    if (fmt == kE12) {
+      uint32_t *d = reinterpret_cast<uint32_t *>(bucket);
+      d[3 * n] = (uint32_t)k.w0;
+      d[3 * n + 1] = (uint32_t)(k.w0 >> 32);
+      d[3 * n + 2] = (uint32_t)k.w1 | 0x80000000u;
+      d[31] = n + 1u;
+    }
+  }
+  if constexpr (FLO <= kE16 && kE16 <= FHI) {
+    if (fmt == kE16) {
+      uint4 v;
+      v.x = (uint32_t)k.w0; v.y = (uint32_t)(k.w0 >> 32);
+      v.z = (uint32_t)k.w1; v.w = (uint32_t)(k.w1 >> 32) | 0x80000000u;
+      reinterpret_cast<uint4 *>(bucket)[n] = v;
+    }
+  }
+  if constexpr (FLO <= kE32 && kE32 <= FHI) {
+    if (fmt == kE32) {
+      uint4 a, b;
+      a.x = (uint32_t)k.w0; a.y = (uint32_t)(k.w0 >> 32);
+      a.z = (uint32_t)k.w1; a.w = (uint32_t)(k.w1 >> 32);
+      b.x = (uint32_t)k.w2; b.y = (uint32_t)(k.w2 >> 32); b.z = 1u; b.w = 0u;
+      reinterpret_cast<uint4 *>(bucket)[2 * n] = a;
+      reinterpret_cast<uint4 *>(bucket)[2 * n + 1] = b;
+    }
   }
 }
 
@@ -202,6 +271,25 @@ __device__ __forceinline__ Key3 flip_key(const Key3 &k, uint32_t jm1) {
   r.w1 ^= (w == 1) ? bit : 0ull;
   r.w2 ^= (w == 2) ? bit : 0ull;
   return r;
+}
+
+// flip_key for keys of at most KWM words (higher words stay as they are).
+template <int KWM>
+__device__ __forceinline__ Key3 flip_key_n(const Key3 &k, uint32_t jm1) {
+  if constexpr (KWM >= 3) {
+    return flip_key(k, jm1);
+  } else {
+    Key3 r = k;
+    const uint64_t bit = 1ull << (jm1 & 63u);
+    if constexpr (KWM == 1) {
+      r.w0 ^= bit;
+    } else {
+      const bool hi = (jm1 >> 6) != 0u;
+      r.w0 ^= hi ? 0ull : bit;
+      r.w1 ^= hi ? bit : 0ull;
+    }
+    return r;
+  }
 }
 
 __device__ __forceinline__ uint32_t key_bit(const Key3 &k, int jm1) {

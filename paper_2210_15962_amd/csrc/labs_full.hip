@@ -380,7 +380,10 @@ __global__ void __launch_bounds__(kBlock) full_walk_kernel(const WalkLaunch a) {
   bool active = slot < n_block;
   const uint32_t colbase = (uint32_t)tid * 4u;
   uint32_t *colw = reinterpret_cast<uint32_t *>(cols);
-  const bool e32 = L > 127;
+  // visited-table entry format of this length (the formats of the class)
+  constexpr int kFLO = entry_format(32 * (NW - 1) + 2);
+  constexpr int kFHI = entry_format(Gm::LMAX);
+  const int efmt = entry_format(L);
   const uint32_t ev = even_c_mask(L);
 
   // ---- first pivot -----------------------------------------------------------
@@ -462,7 +465,7 @@ __global__ void __launch_bounds__(kBlock) full_walk_kernel(const WalkLaunch a) {
 
   // Insert P_1 (the table is empty: first entry of its home bucket).
   if (active && r == 0)
-    store_entry(table + (uint64_t)bucket_of_hash(hP, a.n_buckets) * kBucketBytes, P, e32);
+    store_entry<kFLO, kFHI>(table + (uint64_t)bucket_of_hash(hP, a.n_buckets) * kBucketBytes, 0u, P, efmt);
 
   // Local candidates of lane r: i = r + 1 + G*it; their signs in registers
   // (bit it <-> s_i = -1, 0 past L): the scan reads s_i here, the move toggles it.
@@ -508,7 +511,7 @@ __global__ void __launch_bounds__(kBlock) full_walk_kernel(const WalkLaunch a) {
     int npop = 0;                 // entries popped from tk (head is tk[0])
     int hstat = 0;                // head: 0 unknown, 1 absent, 2 visited
     bool pstarted = false;
-    uint32_t pbucket = 0, pslot = 0;   // pslot: byte offset of the free entry in bucket pbucket
+    uint32_t pbucket = 0, pslot = 0;   // pslot: first free entry of bucket pbucket
     Key3 pkey{0, 0, 0};
     bool need_scan = false;
     bool eager = true;            // probe every head in the next round
@@ -613,7 +616,7 @@ __global__ void __launch_bounds__(kBlock) full_walk_kernel(const WalkLaunch a) {
           pstarted = true;
         }
         uint32_t fs = 0;
-        const int res = scan_bucket(table + (uint64_t)pbucket * kBucketBytes, pkey, e32, fs);
+        const int res = scan_bucket<kFLO, kFHI>(table + (uint64_t)pbucket * kBucketBytes, pkey, efmt, fs);
         if (res == 2) {
           hstat = 2;
         } else if (res == 1) {
@@ -692,7 +695,7 @@ __global__ void __launch_bounds__(kBlock) full_walk_kernel(const WalkLaunch a) {
         const Key3 NP = flip_key(P, im1);
         // the lane that probed the winner inserts it at the slot it found
         const bool owner = hstat == 1 && !lane_empty && npop < K && tk[0] == win;
-        if (owner) store_entry(table + (uint64_t)pbucket * kBucketBytes + pslot, NP, e32);
+        if (owner) store_entry<kFLO, kFHI>(table + (uint64_t)pbucket * kBucketBytes, pslot, NP, efmt);
         P = NP;
         hP ^= zob[im1];
         if ((int)(im1 & (uint32_t)(G - 1)) == r) {

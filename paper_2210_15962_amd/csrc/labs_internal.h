@@ -9,20 +9,26 @@ namespace lsaw {
 constexpr int kLMax = 383;          // D <= 192 free bits, W <= 3 key words
 constexpr int kEnergyLMax = 1024;   // labs_energy: E fits int32 for any +-1 sequence
 constexpr int kBlock = 256;         // threads per workgroup of the walk kernel
-constexpr int kBucketBytes = 64;    // visited-table bucket (one HBM burst)
+constexpr int kBucketBytes = 128;   // visited-table bucket (one 128-byte line)
 
 inline int free_bits(int L) { return (L + 1) / 2; }
 inline int key_words_for(int L) { return (free_bits(L) + 63) / 64; }
 inline int lag_words_for(int L) { return ((L - 1) / 2 + 31) / 32; }
-// 16-byte entries hold keys of up to 127 bits plus an occupancy flag; longer
-// keys use 32-byte entries.
-inline int entry_bytes_for(int L) { return free_bits(L) <= 127 ? 16 : 32; }
+// Visited-table entry formats by key length: 12-byte entries (10 per bucket)
+// hold keys of up to 95 bits plus an occupancy flag, 16-byte entries (8 per
+// bucket) up to 127 bits, 32-byte entries (4 per bucket) up to 191 bits.
+enum : int { kE12 = 0, kE16 = 1, kE32 = 2 };
+__host__ __device__ constexpr int entry_format(int key_bits) {
+  return key_bits <= 95 ? kE12 : key_bits <= 127 ? kE16 : kE32;
+}
+inline int entry_bytes_of(int fmt) { return fmt == kE12 ? 12 : fmt == kE16 ? 16 : 32; }
+inline int entry_bytes_for(int L) { return entry_bytes_of(entry_format(free_bits(L))); }
 
 // Whole search space: keys are the L sequence bits, lags k = 1..L-1.
 constexpr int kFullLMax = 192;      // W <= 3 key words, <= 6 lag words
 inline int full_key_words_for(int L) { return (L + 63) / 64; }
 inline int full_lag_words_for(int L) { return (L - 1 + 31) / 32; }
-inline int full_entry_bytes_for(int L) { return L <= 127 ? 16 : 32; }
+inline int full_entry_bytes_for(int L) { return entry_bytes_of(entry_format(L)); }
 
 struct WalkLaunch {
   const uint64_t *starts;   // device [n][W] or nullptr (seeded starts)
@@ -81,6 +87,7 @@ struct BatchInstanceDev {
   int64_t step_end;         // stop when a walk has made this many moves
   int32_t resume;           // 1: continue from state (tables already filled)
   int32_t pad;
+  uint32_t *cap_steps;      // [n_walks][4] scans per plane cap, or nullptr
 };
 
 struct BatchItemDev {

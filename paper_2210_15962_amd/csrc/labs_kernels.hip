@@ -24,7 +24,7 @@
 //     per word; sum_t s_t C_t over a mask M is 2 * sum_M (c_t XOR -f_t) + |M|
 //     (f_t = 1 where s_t = -1), i.e. XOR, AND and popcount per plane word;
 //   * visited set: exact open-addressing table in HBM keyed on the packed
-//     free bits (64-byte buckets, linear probing, no deletions).
+//     free bits (128-byte buckets, linear probing, no deletions).
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 #include <type_traits>
@@ -50,19 +50,23 @@ __host__ __device__ constexpr int plane_off(int nw, int w) {
 
 // Run table: iterations of the candidate loop grouped into runs of constant
 // lag-word counts; slot kRunSlots-1 holds the number of runs.
-constexpr int kRunSlots = 16;
+constexpr int kRunSlots = 32;   // at most 12 runs occur (every class, lanes per walk and L)
 
 template <int NW>
 struct Geom {
   static constexpr int NWB = (NW + 1) / 2;           // backward lag words
   static constexpr int NWA = NW + NWB + 1;           // words per bit array
   static constexpr int DMAX = (32 * NW + 1) < 192 ? (32 * NW + 1) : 192;
-  static constexpr int DESC = ((9 + NW + 2 * NWB) + 3) & ~3;  // dwords per row
+  // Dwords per row: a multiple of 4 (16-byte row reads) that is 4 (mod 8),
+  // so the rows the lanes of one walk group read at once (candidates j, j+1,
+  // ..., j+7) start on distinct groups of four banks.
+  static constexpr int DESC_FIT = ((9 + NW + 2 * NWB) + 3) & ~3;
+  static constexpr int DESC = DESC_FIT % 8 == 0 ? DESC_FIT + 4 : DESC_FIT;
   static constexpr int NPW = plane_off(NW, NW);      // plane words in total
   static constexpr int BMAX = planes_of(NW, 0);
   // Descriptor rows: D real rows plus dead rows up to a multiple of the
   // lanes per walk (<= 8), so every lane of the candidate loop reads a row.
-  static constexpr int DROWS = DMAX + 8;
+  static constexpr int DROWS = DMAX + 24;
   // The lane columns start on a 256-byte boundary (two-address LDS reads
   // with 256-byte strides need no extra base adjustment).
   static constexpr size_t cols_off() { return ((size_t)DROWS * DESC * 4 + 255) & ~(size_t)255; }
@@ -141,8 +145,8 @@ __device__ __forceinline__ void build_descriptors(uint32_t *desc, int L) {
 #pragma unroll
     for (int i = DS_MASKS + NW + 2 * Gm::NWB; i < Gm::DESC; ++i) row[i] = 0;
   }
-  // Dead rows D+1 .. D+8: all zero, which gives the key ~0 (never chosen).
-  for (int t = (int)threadIdx.x; t < 8 * Gm::DESC; t += blockDim.x) desc[D * Gm::DESC + t] = 0u;
+  // Dead rows D+1 .. DROWS: all zero, which gives the key ~0 (never chosen).
+  for (int t = (int)threadIdx.x; t < (Gm::DROWS - D) * Gm::DESC; t += blockDim.x) desc[D * Gm::DESC + t] = 0u;
 }
 
 // Forward / backward neighbour bit vectors of candidate j, its masks and s_j.
@@ -415,8 +419,9 @@ __device__ __forceinline__ void apply_move_planes(const CandVec<NW> &cv, uint32_
       const uint32_t x = (b == 1) ? u0 : (b == 2) ? u1 : u2;
       const uint32_t p = P[off + b];
       // truth tables over (p, x, carry) = (0xF0, 0xCC, 0xAA): 0x96 = XOR3, 0xE8 = majority
+      const uint32_t c_next = __builtin_amdgcn_bitop3_b32(p, x, carry, 0xE8);
       P[off + b] = __builtin_amdgcn_bitop3_b32(p, x, carry, 0x96);
-      carry = __builtin_amdgcn_bitop3_b32(p, x, carry, 0xE8);
+      carry = c_next;
     }
   });
 }
@@ -466,10 +471,12 @@ __device__ __forceinline__ void run_block(const BlockTask &a, uint8_t *lds) {
     // Runs of iterations with equal lag-word counts: (first i << 8) | code,
     // then a sentinel (nmax << 8).  Past kRunSlots - 2 runs the last run takes
     // the all-words form, which serves any candidate.
+    // A run also ends where the lanes' sign word changes (every 32
+    // iterations), so a run reads one sign word.
     int n = 0, prev = -1;
     for (int i = 0; i < nmax; ++i) {
       const int code = words_of(i, D, Gl, NW);
-      if (code == prev) continue;
+      if (code == prev && (i & 31) != 0) continue;
       if (n == kRunSlots - 2) {
         runs[n - 1] = (runs[n - 1] & ~0xFFu) | (uint32_t)(NW * 8 + Gm::NWB);
         break;
@@ -499,7 +506,13 @@ __device__ __forceinline__ void run_block(const BlockTask &a, uint8_t *lds) {
   bool active = slot < a.n_walks;
   const uint32_t colbase = (uint32_t)tid * 4u;
   uint32_t *colw = reinterpret_cast<uint32_t *>(cols);
-  const bool e32 = D > 127;
+  // Visited-table entry format of this length, within the formats the
+  // kernel's lengths can meet (walk kernels: one class; batches: every class
+  // up to NW).
+  constexpr int kFLO = G > 0 ? entry_format(32 * (NW - 1) + 2) : kE12;
+  constexpr int kFHI = entry_format(Gm::DMAX);
+  const int efmt = entry_format(D);
+  constexpr int KWM = (Gm::DMAX + 63) / 64;        // key words any length of the class needs
 
   // ---- first pivot P_1, or the pivot reached by an earlier launch ----------
   Key3 P{0, 0, 0};
@@ -526,6 +539,8 @@ __device__ __forceinline__ void run_block(const BlockTask &a, uint8_t *lds) {
     P.w1 = start_word(1);
     P.w2 = start_word(2);
   }
+  if constexpr (KWM < 3) P.w2 = 0;
+  if constexpr (KWM < 2) P.w1 = 0;
 
   // ---- sequence bit arrays (Eq. 2 expansion) -------------------------------
   for (int i = 0; i < 4 * Gm::NWA; ++i) colw[i * kBlock + tid] = 0u;
@@ -589,7 +604,7 @@ __device__ __forceinline__ void run_block(const BlockTask &a, uint8_t *lds) {
   uint8_t *table = a.tables + (uint64_t)(active ? slot : 0) * a.table_bytes;
   if (active && a.resume) {
     bestE = ws.bestE;
-    bestP = Key3{ws.bestP[0], ws.bestP[1], ws.bestP[2]};
+    bestP = Key3{ws.bestP[0], KWM >= 2 ? ws.bestP[1] : 0ull, KWM >= 3 ? ws.bestP[2] : 0ull};
     h = ws.h;
     steps = ws.steps;
     prev_jm1 = ws.prev_jm1;
@@ -604,7 +619,7 @@ __device__ __forceinline__ void run_block(const BlockTask &a, uint8_t *lds) {
 
   // Insert P_1 (the table is empty: first entry of its home bucket).
   if (active && !a.resume && r == 0)
-    store_entry(table + (uint64_t)bucket_of_hash(hP, a.n_buckets) * kBucketBytes, P, e32);
+    store_entry<kFLO, kFHI>(table + (uint64_t)bucket_of_hash(hP, a.n_buckets) * kBucketBytes, 0u, P, efmt);
 
   // Local candidates of lane r: j = r + 1 + Gl*i.
   const int ncand = (D - r + Gl - 1) / Gl;       // may be 0 for r >= D
@@ -613,6 +628,7 @@ __device__ __forceinline__ void run_block(const BlockTask &a, uint8_t *lds) {
   // kept in registers: the scan reads s_j from here, the move toggles it.
   constexpr int kGmin = G > 0 ? G : 2;
   constexpr int kSW = ((Gm::DMAX + kGmin - 1) / kGmin + 31) / 32;
+  constexpr int kEXW = ((Gm::DMAX + kGmin - 1) / kGmin + 63) / 64;   // 64-bit exclusion words
   uint32_t smk[kSW];
 #pragma unroll
   for (int w = 0; w < kSW; ++w) smk[w] = 0u;
@@ -625,6 +641,18 @@ __device__ __forceinline__ void run_block(const BlockTask &a, uint8_t *lds) {
       if ((i >> 5) == w) smk[w] |= bit << (i & 31);
     });
   }
+  auto sign_word = [&](int q) -> uint32_t {      // smk[q] for a wave-uniform q
+    if constexpr (kSW == 1) {
+      return smk[0];
+    } else {
+      uint32_t wv = 0u;
+      static_for<0, kSW>([&](auto wc) {
+        constexpr int w = decltype(wc)::value;
+        wv |= smk[w] & (0u - (uint32_t)(q == w));
+      });
+      return wv;
+    }
+  };
   auto sign_of = [&](int i) -> uint32_t {        // ~0 if s_j = -1, else 0 (i uniform)
     if constexpr (kSW == 1) {
       return (uint32_t)__builtin_amdgcn_sbfe((int)smk[0], i & 31, 1);   // i < 32
@@ -640,9 +668,16 @@ __device__ __forceinline__ void run_block(const BlockTask &a, uint8_t *lds) {
   };
   const int nruns = (int)__builtin_amdgcn_readfirstlane(runs[kRunSlots - 1]);
   constexpr uint64_t kMask = WordsMask<NW, G>::value;
-  // Scans per plane cap (walk kernel only; batches do not report them).
-  constexpr bool kCountCaps = G > 0;
-  uint32_t ncap4 = 0u, ncap5 = 0u, ncap6 = 0u, ncap0 = 0u;
+  // Scans per plane cap are wave-uniform while a walk moves: counted once
+  // per wave (scalar registers) and written out for a walk when it stops.
+  uint32_t scap4 = 0u, scap5 = 0u, scap6 = 0u, scap0 = 0u;
+  auto write_caps = [&]() {
+    if (a.cap_steps && slot < a.n_walks && r == 0) {
+      uint4 v;
+      v.x = scap4; v.y = scap5; v.z = scap6; v.w = scap0;
+      *reinterpret_cast<uint4 *>(a.cap_steps + (uint64_t)walk * 4u) = v;
+    }
+  };
   const bool tracing = active && walk < a.n_trace;
 
   // Every walk still moving has made exactly step_begin moves (trapped walks
@@ -655,10 +690,14 @@ __device__ __forceinline__ void run_block(const BlockTask &a, uint8_t *lds) {
     uint64_t ex0 = 0ull, ex1 = 0ull, ex2 = 0ull;
     auto exclude = [&](uint32_t li) {
       const uint64_t bit = 1ull << (li & 63u);
-      const uint32_t q = li >> 6;
-      ex0 |= (q == 0u) ? bit : 0ull;
-      ex1 |= (q == 1u) ? bit : 0ull;
-      ex2 |= (q == 2u) ? bit : 0ull;
+      if constexpr (kEXW == 1) {
+        ex0 |= bit;
+      } else {
+        const uint32_t q = li >> 6;
+        ex0 |= (q == 0u) ? bit : 0ull;
+        ex1 |= (q == 1u) ? bit : 0ull;
+        if constexpr (kEXW >= 3) ex2 |= (q == 2u) ? bit : 0ull;
+      }
     };
     if (prev_jm1 != 0xFFFFFFFFu && (int)(prev_jm1 % Gl) == r) exclude(prev_jm1 / Gl);
 
@@ -667,7 +706,7 @@ __device__ __forceinline__ void run_block(const BlockTask &a, uint8_t *lds) {
     int npop = 0;                 // entries popped from tk (head is tk[0])
     int hstat = 0;                // head: 0 unknown, 1 absent, 2 visited
     bool pstarted = false;
-    uint32_t pbucket = 0, pslot = 0;   // pslot: byte offset of the free entry in bucket pbucket
+    uint32_t pbucket = 0, pslot = 0;   // pslot: first free entry of bucket pbucket
     Key3 pkey{0, 0, 0};
     bool need_scan = false;
     bool eager = true;            // probe every head in the next round
@@ -679,14 +718,10 @@ __device__ __forceinline__ void run_block(const BlockTask &a, uint8_t *lds) {
 #pragma unroll
     for (int i = 0; i < K; ++i) tk[i] = kKeyMax;
     const int bp = wave_plane_cap<NW>(Pl, active);
-    if constexpr (kCountCaps) {
-      if (active) {
-        ncap4 += bp == 4 ? 1u : 0u;
-        ncap5 += bp == 5 ? 1u : 0u;
-        ncap6 += bp == 6 ? 1u : 0u;
-        ncap0 += bp == 0 ? 1u : 0u;
-      }
-    }
+    scap4 += bp == 4 ? 1u : 0u;
+    scap5 += bp == 5 ? 1u : 0u;
+    scap6 += bp == 6 ? 1u : 0u;
+    scap0 += bp == 0 ? 1u : 0u;
 #pragma unroll 1
     for (int sr = 0; sr < nruns; ++sr) {
       const uint32_t e0 = __builtin_amdgcn_readfirstlane(runs[sr]);
@@ -694,6 +729,8 @@ __device__ __forceinline__ void run_block(const BlockTask &a, uint8_t *lds) {
       const int ie = (int)(__builtin_amdgcn_readfirstlane(runs[sr + 1]) >> 8);
       with_words<NW, kMask>((int)(e0 & 0xFFu), [&](auto Fc, auto Bc) __attribute__((always_inline)) {
         constexpr int F = decltype(Fc)::value, B = decltype(Bc)::value;
+        // the run's sign word (runs do not cross a multiple of 32 iterations)
+        const uint32_t swr = sign_word(ib >> 5);
         auto scan = [&](auto BPc) __attribute__((always_inline)) {
           constexpr int BPv = decltype(BPc)::value;
 #pragma unroll 1
@@ -701,7 +738,7 @@ __device__ __forceinline__ void run_block(const BlockTask &a, uint8_t *lds) {
             // j > D reads a dead row whose key ~0 leaves the top-K unchanged
             const int j = r + 1 + Gl * i;
             topk_insert<K>(tk, eval_key<NW, F, B, BPv, (G > 0)>(desc + (j - 1) * Gm::DESC, cols, colbase, Pl,
-                                                       sign_of(i)));
+                                                       (uint32_t)__builtin_amdgcn_sbfe((int)swr, i & 31, 1)));
           }
         };
         if (bp == 4) scan(std::integral_constant<int, 4>{});
@@ -743,8 +780,10 @@ __device__ __forceinline__ void run_block(const BlockTask &a, uint8_t *lds) {
             constexpr int F = decltype(Fc)::value, B = decltype(Bc)::value;
             // select with masks: a select chain becomes a stack lookup table
             auto ex_word = [&](int qw) {
-              return (ex0 & (0ull - (uint64_t)(qw == 0))) | (ex1 & (0ull - (uint64_t)(qw == 1))) |
-                     (ex2 & (0ull - (uint64_t)(qw == 2)));
+              if constexpr (kEXW == 1) return ex0;
+              else
+                return (ex0 & (0ull - (uint64_t)(qw == 0))) | (ex1 & (0ull - (uint64_t)(qw == 1))) |
+                       (ex2 & (0ull - (uint64_t)(qw == 2)));
             };
             uint64_t xw = ex_word(ib >> 6) >> (ib & 63);
 #pragma unroll 1
@@ -777,12 +816,12 @@ __device__ __forceinline__ void run_block(const BlockTask &a, uint8_t *lds) {
       const bool head_valid = !done && !lane_empty && npop < K && head != kKeyMax;
       auto probe_head = [&](uint32_t hk) {
         if (!pstarted) {
-          pkey = flip_key(P, hk & 0xFFu);
+          pkey = flip_key_n<KWM>(P, hk & 0xFFu);
           pbucket = bucket_of_hash(hP ^ zob[hk & 0xFFu], a.n_buckets);
           pstarted = true;
         }
         uint32_t slot = 0;
-        const int res = scan_bucket(table + (uint64_t)pbucket * kBucketBytes, pkey, e32, slot);
+        const int res = scan_bucket<kFLO, kFHI>(table + (uint64_t)pbucket * kBucketBytes, pkey, efmt, slot);
         if (res == 2) {
           hstat = 2;
         } else if (res == 1) {
@@ -792,21 +831,23 @@ __device__ __forceinline__ void run_block(const BlockTask &a, uint8_t *lds) {
           pbucket = (pbucket + 1u == a.n_buckets) ? 0u : pbucket + 1u;
         }
       };
-      if (head_valid && hstat == 0 && eager) probe_head(head);
-      eager = false;
-      // Every head already known to be visited leaves its list now (a visited
-      // neighbour is never chosen), so the merge sees only heads that are new
-      // or not yet probed: a walk needs another round only when the group's
-      // best remaining head has not been probed.
-      if (head_valid && hstat == 2) {
-        exclude((head & 0xFFu) / Gl);
+      // Removes the head (found visited).
+      auto pop_head = [&]() {
+        exclude((tk[0] & 0xFFu) / Gl);
 #pragma unroll
         for (int q = 0; q + 1 < K; ++q) tk[q] = tk[q + 1];
         tk[K - 1] = kKeyMax;
         ++npop;
         hstat = 0;
         pstarted = false;
-      }
+      };
+      if (head_valid && hstat == 0 && eager) probe_head(head);
+      eager = false;
+      // Every head already known to be visited leaves its list now (a visited
+      // neighbour is never chosen), so the merge sees only heads that are new
+      // or not yet probed: a walk needs another round only when the group's
+      // best remaining head has not been probed.
+      if (head_valid && hstat == 2) pop_head();
       const uint32_t cur = tk[0];
       const bool cur_valid = !done && !lane_empty && npop < K && cur != kKeyMax;
       // (3) merge the heads of the group.
@@ -828,15 +869,7 @@ __device__ __forceinline__ void run_block(const BlockTask &a, uint8_t *lds) {
           done = true;          // the group's best remaining candidate is new
           win = gmin;
         } else if (ostat == 3u) {
-          if (owner) {
-            exclude((cur & 0xFFu) / Gl);
-#pragma unroll
-            for (int i = 0; i + 1 < K; ++i) tk[i] = tk[i + 1];
-            tk[K - 1] = kKeyMax;
-            ++npop;
-            hstat = 0;
-            pstarted = false;
-          }
+          if (owner) pop_head();
         }
         if (!done && npop >= K && !lane_empty) need_scan = true;
       }
@@ -848,6 +881,7 @@ __device__ __forceinline__ void run_block(const BlockTask &a, uint8_t *lds) {
       if (win == kKeyMax) {
         active = false;         // trapped walk stops here
         trapped = true;
+        write_caps();           // the scans this walk took, up to its last
       } else {
         const uint32_t jm1 = win & 0xFFu;
         const int32_t dE = 8 * ((int32_t)(win >> 8) - kBias);
@@ -868,10 +902,10 @@ __device__ __forceinline__ void run_block(const BlockTask &a, uint8_t *lds) {
           colw[(af * Gm::NWA + (rr >> 5)) * kBlock + tid] ^= 1u << (rr & 31);
           colw[((af + 2) * Gm::NWA + (rv >> 5)) * kBlock + tid] ^= 1u << (rv & 31);
         }
-        const Key3 NP = flip_key(P, jm1);
+        const Key3 NP = flip_key_n<KWM>(P, jm1);
         // the lane that probed the winner inserts it at the slot it found
         const bool owner = hstat == 1 && !lane_empty && npop < K && tk[0] == win;
-        if (owner) store_entry(table + (uint64_t)pbucket * kBucketBytes + pslot, NP, e32);
+        if (owner) store_entry<kFLO, kFHI>(table + (uint64_t)pbucket * kBucketBytes, pslot, NP, efmt);
         P = NP;
         hP ^= zob[jm1];
         if ((int)(jm1 & (uint32_t)(Gl - 1)) == r) {
@@ -906,13 +940,7 @@ __device__ __forceinline__ void run_block(const BlockTask &a, uint8_t *lds) {
     o.trapped = trapped ? 1u : 0u;
     a.state[walk] = o;
   }
-  if constexpr (kCountCaps) {
-    if (a.cap_steps && slot < a.n_walks && r == 0) {
-      uint4 v;
-      v.x = ncap4; v.y = ncap5; v.z = ncap6; v.w = ncap0;
-      *reinterpret_cast<uint4 *>(a.cap_steps + (uint64_t)walk * 4u) = v;
-    }
-  }
+  if (!trapped) write_caps();   // moved at every step of this launch
   if (finished && slot < a.n_walks && r == 0) {
     a.best_seq[walk * KW] = bestP.w0;
     if (KW > 1) a.best_seq[walk * KW + 1] = bestP.w1;
@@ -986,7 +1014,7 @@ __global__ void __launch_bounds__(kBlock) batch_kernel(const BatchLaunch b) {
     t.trace_j = in.trace_j;
     t.trace_E = in.trace_E;
     t.n_trace = in.n_trace;
-    t.cap_steps = nullptr;
+    t.cap_steps = in.cap_steps;
     t.tables = in.tables ? in.tables + (uint64_t)item.walk_begin * in.table_bytes : arena;
     t.table_bytes = in.table_bytes;
     t.n_buckets = in.n_buckets;

@@ -410,7 +410,7 @@ def full_walks(L: int, n_walks: int, walk_len: int, seed: int = 0, starts_t=None
 
 
 # ----------------------------------------------------------- mixed-L batches
-def _alloc_outputs(L, n_walks, walk_len, n_trace, device="cuda"):
+def _alloc_outputs(L, n_walks, walk_len, n_trace, device="cuda", cap_steps=False):
     import torch
     W = key_words(L)
     res = {
@@ -422,18 +422,20 @@ def _alloc_outputs(L, n_walks, walk_len, n_trace, device="cuda"):
     if n_trace:
         res["trace_j"] = torch.zeros((n_trace, walk_len), dtype=torch.int16, device=device)
         res["trace_E"] = torch.zeros((n_trace, walk_len), dtype=torch.int32, device=device)
+    if cap_steps:
+        res["cap_steps"] = torch.zeros((n_walks, 4), dtype=torch.int32, device=device)
     return res
 
 
 def make_instances(specs, results):
     """ctypes array of labs_instance from dicts (L, n_walks, walk_len, seed, starts_t,
-    lanes_per_walk, load_factor, n_trace) and their output tensors."""
+    lanes_per_walk, load_factor, n_trace, cap_steps) and their output tensors."""
     arr = (Instance * max(len(specs), 1))()
     for i, (sp, res) in enumerate(zip(specs, results)):
         st = sp.get("starts_t")
         out = WalkOut(_dptr(res["best_seq"]), _dptr(res["best_E"]), _dptr(res["steps_done"]),
                       _dptr(res["digest"]), _dptr(res.get("trace_j")), _dptr(res.get("trace_E")),
-                      int(sp.get("n_trace", 0)))
+                      int(sp.get("n_trace", 0)), _dptr(res.get("cap_steps")))
         arr[i] = Instance(int(sp["L"]), int(sp.get("lanes_per_walk", 0)), int(sp["n_walks"]),
                           int(sp["walk_len"]), int(sp.get("seed", 0)) & 0xFFFFFFFFFFFFFFFF,
                           _dptr(st), float(sp.get("load_factor", 0.0)), out)
@@ -451,7 +453,8 @@ def batch_workspace_bytes(specs, results=None) -> int:
 def walks_batch(specs, workspace=None, stream=None, device="cuda"):
     """Run several instances (list of dicts, see make_instances) in one launch.
     Returns one result dict per instance, like walks()."""
-    results = [_alloc_outputs(sp["L"], sp["n_walks"], sp["walk_len"], sp.get("n_trace", 0), device)
+    results = [_alloc_outputs(sp["L"], sp["n_walks"], sp["walk_len"], sp.get("n_trace", 0), device,
+                              sp.get("cap_steps", False))
                for sp in specs]
     arr = make_instances(specs, results)
     if workspace is None:
@@ -471,7 +474,7 @@ class BatchGraph:
     def __init__(self, specs, workspace=None, device="cuda"):
         self.specs = specs
         self.results = [_alloc_outputs(sp["L"], sp["n_walks"], sp["walk_len"], sp.get("n_trace", 0),
-                                       device) for sp in specs]
+                                       device, sp.get("cap_steps", False)) for sp in specs]
         self._arr = make_instances(specs, self.results)
         if workspace is None:
             b = U64(0)

@@ -72,17 +72,21 @@ def test_host_helpers_reject_bad_input():
 
 
 def test_workspace_sizing():
-    # one bucket of 64 bytes holds 4 entries of 16 bytes (D <= 127) or 2 of 32
+    # one bucket of 128 bytes holds 10 entries of 12 bytes (D <= 95), 8 of 16
+    # (D <= 127) or 4 of 32
     b = labs.workspace_bytes(27, 64, 4096)
     per_walk = b // 64
-    assert per_walk % 64 == 0
-    assert per_walk // 64 * 4 * 0.5 >= 4097            # load factor 0.5 by default
+    assert per_walk % 128 == 0
+    assert per_walk // 128 * 10 * 0.5 >= 4097           # load factor 0.5 by default
+    assert (per_walk // 128 - 1) * 10 * 0.5 < 4097
     assert labs.min_workspace_bytes(27, 4096) == per_walk
     p = labs.make_plan(load_factor=0.25)
-    assert labs.min_workspace_bytes(27, 4096, p) >= 2 * per_walk - 64
+    assert labs.min_workspace_bytes(27, 4096, p) >= 2 * per_walk - 128
     assert labs.workspace_bytes(27, 64, 4096, labs.make_plan(max_concurrent=8)) == 8 * per_walk
-    # 32-byte entries from D = 128 on
-    assert labs.min_workspace_bytes(255, 1000) >= labs.min_workspace_bytes(253, 1000) * 2 - 64
+    # 16-byte entries from D = 96 on, 32-byte entries from D = 128 on
+    ratio16 = labs.min_workspace_bytes(191, 100_000) / labs.min_workspace_bytes(189, 100_000)
+    assert abs(ratio16 - 10 / 8) < 1e-3
+    assert labs.min_workspace_bytes(255, 1000) >= labs.min_workspace_bytes(253, 1000) * 2 - 128
     assert labs.workspace_bytes(27, 0, 10) == 0
 
 
@@ -164,17 +168,6 @@ def test_serve_validation_before_any_device_call():
     assert lib.labs_serve_destroy(None) == labs.LABS_OK
 
 
-def test_batch_rejects_cap_counts():
-    lib = labs.lib()
-    out = {"best_seq": None, "best_E": None, "steps_done": None, "digest": None}
-    arr = labs.make_instances([dict(L=27, n_walks=4, walk_len=10)], [out])
-    arr[0].out.best_seq = arr[0].out.best_E = arr[0].out.steps_done = 1
-    arr[0].out.cap_steps = 1
-    ws = ctypes.c_void_p(1)
-    assert lib.labs_walks_batch(arr, 1, ws, 1 << 30, None) == labs.LABS_EINVAL
-    assert b"cap_steps" in lib.labs_last_error()
-
-
 def test_stopping_model_matches_oracle():
     import math
     for L in [71, 101, 121, 171, 223, 247]:
@@ -229,10 +222,13 @@ def test_full_space_sizes_and_validation_before_any_launch():
         assert labs.full_key_words(L) == O.full_key_words(L)
     for bad in [-1, 0, 1, 2, 193, 383]:
         assert labs.full_key_words(bad) == 0
-    # 16-byte entries up to L = 127, then 32-byte entries
+    # 12-byte entries up to L = 95, 16-byte entries up to L = 127, then 32-byte entries
+    b95 = labs.full_workspace_bytes(95, 1, 100_000)
+    b96 = labs.full_workspace_bytes(96, 1, 100_000)
+    assert abs(b96 / b95 - 10 / 8) < 1e-3
     b127 = labs.full_workspace_bytes(127, 1, 1000)
     b128 = labs.full_workspace_bytes(128, 1, 1000)
-    assert b128 >= 2 * b127 - 64 and b127 // 64 * 4 * 0.5 >= 1001
+    assert b128 >= 2 * b127 - 128 and b127 // 128 * 8 * 0.5 >= 1001
     assert labs.full_workspace_bytes(64, 10, 100, labs.make_plan(max_concurrent=4)) == \
         4 * labs.full_workspace_bytes(64, 1, 100)
     lib = labs.lib()
@@ -254,23 +250,23 @@ def test_full_space_sizes_and_validation_before_any_launch():
     assert lib.labs_full_walks(None, 64, 0, 10, 0, ref(out), ws, 0, None, None) == labs.LABS_OK
 
 
-def test_tables_beyond_2_to_26_buckets_are_sized_in_64_bits():
-    """Visited tables of 2^26 buckets and more (over 4 GiB per walk) are valid
+def test_tables_over_4_gib_are_sized_in_64_bits():
+    """Visited tables of 2^25 buckets and more (over 4 GiB per walk) are valid
     sizes: the per-walk size is computed in 64 bits and only a bucket count of
     2^32 or more is refused (the kernels index buckets in 32 bits and bytes in 64)."""
-    lf = labs.make_plan(load_factor=0.0001)
+    lf = labs.make_plan(load_factor=0.00008)
     keys = 30_001                                   # walk_len + 1 pivots
     per_walk = labs.min_workspace_bytes(101, 30_000, lf)
-    n_buckets = per_walk // 64
-    assert n_buckets >= keys / (4 * 0.0001) and n_buckets >= 1 << 26
+    n_buckets = per_walk // 128
+    assert n_buckets >= keys / (10 * 0.00008) and n_buckets >= 1 << 25
     assert per_walk > 1 << 32
     assert labs.workspace_bytes(101, 3, 30_000, lf) == 3 * per_walk
     assert labs.full_workspace_bytes(100, 2, 30_000, lf) == 2 * labs.full_workspace_bytes(100, 1, 30_000, lf)
     assert labs.full_workspace_bytes(100, 1, 30_000, lf) > 1 << 32
-    # 2^31 moves at load 0.1 would need more than 2^32 buckets
+    # 2^31 moves at load 0.04 would need more than 2^32 buckets
     lib = labs.lib()
     nb = labs.U64(0)
-    huge = labs.make_plan(load_factor=0.1)
+    huge = labs.make_plan(load_factor=0.04)
     assert lib.labs_walks_workspace_bytes(101, 1, 1 << 31, ctypes.byref(huge), ctypes.byref(nb)) == labs.LABS_EINVAL
     assert b"too large" in lib.labs_last_error()
     assert lib.labs_full_walks_workspace_bytes(100, 1, 1 << 31, ctypes.byref(huge), ctypes.byref(nb)) == labs.LABS_EINVAL

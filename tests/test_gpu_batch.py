@@ -179,3 +179,22 @@ def test_class_groups_sequential_and_concurrent_agree():
         for a, c in zip(res, alone):
             _assert_same(a, c)
     g.close()
+
+
+def test_batch_reports_one_scan_per_move():
+    """Batches report each walk's neighbourhood scans by plane cap: one scan per
+    move, plus the last scan of a trapped walk."""
+    labs = _labs()
+    specs = _specs(6, 61, 301, n_walks=[100, 257], walk_len=900, seed=13)
+    specs.append(dict(L=7, n_walks=40, walk_len=100, seed=7, lanes_per_walk=2))   # traps
+    for sp in specs:
+        sp["cap_steps"] = True
+    res = labs.walks_batch(specs)
+    torch.cuda.synchronize()
+    for sp, r in zip(specs, res):
+        caps = r["cap_steps"].cpu().numpy().astype(np.int64).sum(1)
+        sd = r["steps_done"].cpu().numpy()
+        trapped = sd < sp["walk_len"]
+        np.testing.assert_array_equal(caps, sd + trapped.astype(np.int64))
+        _assert_same(r, _standalone(sp))
+    assert (res[-1]["steps_done"].cpu().numpy() < 100).any()       # some L = 7 walk trapped
