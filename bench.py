@@ -22,9 +22,9 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# Headline workload: walks at L = 151.  At load factor 0.67 the 65,536 visited
-# tables (131,073 keys each, 16-byte entries) take 191 GiB, so every walk stays
-# resident in one launch.
+# Headline workload: walks at L = 151.  At load factor 0.55 the 65,536 visited
+# tables (131,073 keys each, 12-byte entries, 10 per 128-byte bucket) take
+# 186 GiB, so every walk stays resident in one launch.
 WORKLOAD = dict(L=151, n_walks=65536, walk_len=131072)
 
 # MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz, one 32-bit lane-op per cycle.

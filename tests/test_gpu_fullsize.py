@@ -98,7 +98,7 @@ def test_config2_L101_16384_walks_65536_moves():
 def test_config3_L151_65536_walks_131072_moves_bench_plan():
     labs = _labs()
     L, n, steps = 151, 65536, 131072
-    plan = labs.make_plan(lanes_per_walk=4, load_factor=0.67, max_concurrent=65536)
+    plan = labs.make_plan(lanes_per_walk=4, load_factor=0.55, max_concurrent=65536)
     ws = labs.alloc_workspace(labs.workspace_bytes(L, n, steps, plan))
     res = labs.walks(L, n, steps, seed=0, plan=plan, workspace=ws, n_trace=4)
     torch.cuda.synchronize()
