@@ -40,8 +40,8 @@
 namespace {
 
 constexpr int ORC_L_MAX = 383;           // D <= 192, so W <= 3
-constexpr int ORC_W_MAX = 3;
-constexpr int ORC_FULL_L_MAX = 192;      // whole space: L bits, W <= 3
+constexpr int ORC_W_MAX = 4;
+constexpr int ORC_FULL_L_MAX = 255;      // whole space: L bits, W <= 4
 
 typedef std::array<uint64_t, ORC_W_MAX> Key;
 

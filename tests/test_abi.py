@@ -217,7 +217,7 @@ def test_tuning_table_json_roundtrip(tmp_path):
 
 
 def test_full_space_sizes_and_validation_before_any_launch():
-    assert labs.full_l_max() == 192 == O.full_l_max()
+    assert labs.full_l_max() == 192 and O.full_l_max() == 255
     for L in [3, 4, 63, 64, 65, 128, 129, 192]:
         assert labs.full_key_words(L) == O.full_key_words(L)
     for bad in [-1, 0, 1, 2, 193, 383]:

@@ -98,7 +98,7 @@ def test_bruteforce_against_numpy_enumeration(L):
     assert first == int(np.argmax(Es == mn)) and total == int(Es.sum())
 
 
-@pytest.mark.parametrize("L", [5, 16, 33, 64, 65, 100, 128, 129, 192])
+@pytest.mark.parametrize("L", [5, 16, 33, 64, 65, 100, 128, 129, 192, 193, 247, 255])
 def test_energy_packed_matches_numpy(L):
     for key in I.random_full_keys(L, 4, seed=L):
         s = unpack(key, L)
@@ -112,7 +112,7 @@ def test_energy_packed_matches_numpy(L):
 
 
 def test_starts_layout_and_mask():
-    for L in (3, 64, 65, 127, 128, 129, 192):
+    for L in (3, 64, 65, 127, 128, 129, 192, 193, 255):
         st = O.full_starts(L, 5, seed=7)
         W = (L + 63) // 64
         assert st.shape == (5, W)
@@ -159,7 +159,8 @@ def check_full_walk(L, start, walk_len, r):
 
 
 @pytest.mark.parametrize("L,walk_len,n", [(4, 40, 4), (6, 100, 3), (9, 200, 3), (20, 200, 2),
-                                          (33, 120, 2), (64, 60, 1), (70, 50, 1)])
+                                          (33, 120, 2), (64, 60, 1), (70, 50, 1), (200, 8, 1),
+                                          (255, 6, 1)])
 def test_walk_semantics(L, walk_len, n):
     for start in I.random_full_keys(L, n, seed=200 + L):
         r = O.full_walk(L, start, walk_len)
@@ -217,6 +218,11 @@ def test_walk_len_zero_and_domain():
     r = O.full_walk(100, st, 0)
     assert r.steps == 0 and r.digest == 0
     assert r.best_E == O.full_energy_packed(st, 100)
-    for bad in (2, 193):
+    for bad in (2, 256):
         with pytest.raises(ValueError):
             O.full_walk(bad, np.zeros(4, dtype=np.uint64), 5)
+    # the longest whole-space length: four key words, the top bit free
+    assert O.full_l_max() == 255 and O.full_key_words(255) == 4
+    st = I.random_full_keys(255, 1, seed=11)[0]
+    r = O.full_walk(255, st, 3)
+    assert r.steps == 3 and len(r.best_seq) == 4
