@@ -471,6 +471,8 @@ def main():
     ap.add_argument("--paper-walks", type=int, default=262144)
     ap.add_argument("--mixed-batch", action="store_true",
                     help="256-instance mixed-L batch (hipGraph replays) only, default then autotuned")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="with --mixed-batch: the default plan only (no autotuned leg)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -501,7 +503,8 @@ def main():
         return
 
     if args.mixed_batch:
-        for tune in (False, True):
+        calibration_copy(args.calibration_copy_mib)
+        for tune in ((False,) if args.no_autotune else (False, True)):
             print(json.dumps(run_mixed_batch(args.steps, args.warmup, tune)), flush=True)
         return
 

@@ -987,8 +987,13 @@ __global__ void __launch_bounds__(kBlock) walk_kernel(const WalkLaunch w) {
 // the variant compiled for its lag-word class and lanes per walk.
 // ---------------------------------------------------------------------------
 
+// Waves per SIMD the batch kernel of a class is built for: classes up to 4
+// fit three (168 VGPRs), the longer ones two.
 template <int NWMAX>
-__global__ void __launch_bounds__(kBlock) batch_kernel(const BatchLaunch b) {
+struct BatchOccupancy { static constexpr int value = NWMAX <= 4 ? 3 : 2; };
+
+template <int NWMAX>
+__global__ void __launch_bounds__(kBlock, BatchOccupancy<NWMAX>::value) batch_kernel(const BatchLaunch b) {
   extern __shared__ __align__(16) uint8_t lds[];
   __shared__ int64_t s_item;
   uint8_t *arena = b.arena + (uint64_t)blockIdx.x * b.arena_bytes;
