@@ -183,7 +183,7 @@ int32_t labs_walks_noalloc(const uint64_t *starts, int32_t L, int64_t n_walks,
 /*
  * Whole search space (the sokol_full solver that Sec. 5 names as future
  * work): the walks of labs_walks over all 2^L binary sequences of any length
- * L, 3 <= L <= labs_full_l_max() (192), even or odd.  The pivot is the whole
+ * L, 3 <= L <= labs_full_l_max() (255), even or odd.  The pivot is the whole
  * sequence, packed in W = ceil(L/64) words (bit i-1 = s_i, 1 means -1, bits
  * at L and above zero); a neighbour negates one sequence position, so every
  * move scores all L neighbours by Eq. 1 (computed incrementally, exactly) and
@@ -198,7 +198,7 @@ int32_t labs_walks_noalloc(const uint64_t *starts, int32_t L, int64_t n_walks,
  *   labs_full_walks: arguments, ownership and layout as labs_walks (device
  *     pointers, asynchronous on stream, workspace contents unspecified on
  *     exit); plan->lanes_per_walk must be 0 or 4.
- * Errors: LABS_EINVAL (L outside [3, 192], n_walks < 0, walk_len < 0 or above
+ * Errors: LABS_EINVAL (L outside [3, 255], n_walks < 0, walk_len < 0 or above
  * 2^31, NULL required pointer, bad plan, workspace below one table),
  * LABS_EDEVICE (launch failure).
  */

@@ -132,7 +132,8 @@ constexpr int32_t kBias = 1 << 23;      // bias of the scaled energy change insi
 // ---------------------------------------------------------------------------
 // Visited table
 // ---------------------------------------------------------------------------
-struct Key3 { uint64_t w0, w1, w2; };
+// A packed key of up to 255 bits (bit b in word b / 64).
+struct Key { uint64_t w0, w1, w2, w3; };
 
 // Bucket of a key: an XOR-linear (Zobrist) hash -- the XOR of one random
 // 32-bit word per set key bit -- mapped onto [0, n_buckets) by a
@@ -152,7 +153,7 @@ __device__ __forceinline__ uint32_t bucket_of_hash(uint32_t h, uint32_t n_bucket
 //         64-94 with bit 31 of the third dword set when the entry is used);
 //         dword 31 holds the number of entries in the bucket;
 //   kE16: 8 entries of 16 bytes (key bits 0-126, bit 127 set when used);
-//   kE32: 4 entries of 32 bytes (key bits 0-191, dword 6 nonzero when used).
+//   kE32: 4 entries of 32 bytes (key bits 0-254, bit 255 set when used).
 // Entries fill in order and are never deleted, so a present key lies before
 // the first free entry.
 struct Bucket { uint4 q[8]; };
@@ -176,7 +177,7 @@ __device__ __forceinline__ uint32_t bucket_dword(const Bucket &b, int i) {
 // of the first free entry), 0 = bucket full without the key.  No early exits:
 // every entry is compared.
 template <int FLO, int FHI>
-__device__ __forceinline__ int test_bucket(const Bucket &bk, const Key3 &k, int fmt, uint32_t &n) {
+__device__ __forceinline__ int test_bucket(const Bucket &bk, const Key &k, int fmt, uint32_t &n) {
   const uint32_t k0 = (uint32_t)k.w0, k1 = (uint32_t)(k.w0 >> 32);
   const uint32_t k2 = (uint32_t)k.w1, k3 = (uint32_t)(k.w1 >> 32);
   bool found = false;
@@ -210,14 +211,15 @@ __device__ __forceinline__ int test_bucket(const Bucket &bk, const Key3 &k, int 
   if constexpr (FLO <= kE32 && kE32 <= FHI) {
     if (fmt == kE32) {
       const uint32_t k4 = (uint32_t)k.w2, k5 = (uint32_t)(k.w2 >> 32);
+      const uint32_t k6 = (uint32_t)k.w3, k7f = (uint32_t)(k.w3 >> 32) | 0x80000000u;
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
-        const uint32_t used = bucket_dword(bk, 8 * e + 6);
         const uint32_t x = (bucket_dword(bk, 8 * e) ^ k0) | (bucket_dword(bk, 8 * e + 1) ^ k1) |
                            (bucket_dword(bk, 8 * e + 2) ^ k2) | (bucket_dword(bk, 8 * e + 3) ^ k3) |
-                           (bucket_dword(bk, 8 * e + 4) ^ k4) | (bucket_dword(bk, 8 * e + 5) ^ k5);
-        found = found || (x == 0u && used != 0u);
-        cnt += used != 0u ? 1u : 0u;
+                           (bucket_dword(bk, 8 * e + 4) ^ k4) | (bucket_dword(bk, 8 * e + 5) ^ k5) |
+                           (bucket_dword(bk, 8 * e + 6) ^ k6) | (bucket_dword(bk, 8 * e + 7) ^ k7f);
+        found = found || x == 0u;
+        cnt += bucket_dword(bk, 8 * e + 7) >> 31;
       }
       cap = 4u;
     }
@@ -227,13 +229,13 @@ __device__ __forceinline__ int test_bucket(const Bucket &bk, const Key3 &k, int 
 }
 
 template <int FLO, int FHI>
-__device__ __forceinline__ int scan_bucket(const uint8_t *bucket, const Key3 &k, int fmt, uint32_t &n) {
+__device__ __forceinline__ int scan_bucket(const uint8_t *bucket, const Key &k, int fmt, uint32_t &n) {
   return test_bucket<FLO, FHI>(load_bucket(bucket), k, fmt, n);
 }
 
 // Stores key k as entry n of a bucket (n = the first free entry found by its probe).
 template <int FLO, int FHI>
-__device__ __forceinline__ void store_entry(uint8_t *bucket, uint32_t n, const Key3 &k, int fmt) {
+__device__ __forceinline__ void store_entry(uint8_t *bucket, uint32_t n, const Key &k, int fmt) {
   if constexpr (FLO <= kE12 && kE12 <= FHI) {
     if (fmt == kE12) {
       uint32_t *d = reinterpret_cast<uint32_t *>(bucket);
@@ -256,30 +258,40 @@ __device__ __forceinline__ void store_entry(uint8_t *bucket, uint32_t n, const K
       uint4 a, b;
       a.x = (uint32_t)k.w0; a.y = (uint32_t)(k.w0 >> 32);
       a.z = (uint32_t)k.w1; a.w = (uint32_t)(k.w1 >> 32);
-      b.x = (uint32_t)k.w2; b.y = (uint32_t)(k.w2 >> 32); b.z = 1u; b.w = 0u;
+      b.x = (uint32_t)k.w2; b.y = (uint32_t)(k.w2 >> 32);
+      b.z = (uint32_t)k.w3; b.w = (uint32_t)(k.w3 >> 32) | 0x80000000u;
       reinterpret_cast<uint4 *>(bucket)[2 * n] = a;
       reinterpret_cast<uint4 *>(bucket)[2 * n + 1] = b;
     }
   }
 }
 
-__device__ __forceinline__ Key3 flip_key(const Key3 &k, uint32_t jm1) {
-  Key3 r = k;
+__device__ __forceinline__ Key flip_key(const Key &k, uint32_t jm1) {
+  Key r = k;
   const uint64_t bit = 1ull << (jm1 & 63u);
   const uint32_t w = jm1 >> 6;
   r.w0 ^= (w == 0) ? bit : 0ull;
   r.w1 ^= (w == 1) ? bit : 0ull;
   r.w2 ^= (w == 2) ? bit : 0ull;
+  r.w3 ^= (w == 3) ? bit : 0ull;
   return r;
 }
 
 // flip_key for keys of at most KWM words (higher words stay as they are).
 template <int KWM>
-__device__ __forceinline__ Key3 flip_key_n(const Key3 &k, uint32_t jm1) {
-  if constexpr (KWM >= 3) {
+__device__ __forceinline__ Key flip_key_n(const Key &k, uint32_t jm1) {
+  if constexpr (KWM >= 4) {
     return flip_key(k, jm1);
+  } else if constexpr (KWM == 3) {
+    Key r = k;
+    const uint64_t bit = 1ull << (jm1 & 63u);
+    const uint32_t w = jm1 >> 6;
+    r.w0 ^= (w == 0) ? bit : 0ull;
+    r.w1 ^= (w == 1) ? bit : 0ull;
+    r.w2 ^= (w == 2) ? bit : 0ull;
+    return r;
   } else {
-    Key3 r = k;
+    Key r = k;
     const uint64_t bit = 1ull << (jm1 & 63u);
     if constexpr (KWM == 1) {
       r.w0 ^= bit;
@@ -292,8 +304,8 @@ __device__ __forceinline__ Key3 flip_key_n(const Key3 &k, uint32_t jm1) {
   }
 }
 
-__device__ __forceinline__ uint32_t key_bit(const Key3 &k, int jm1) {
-  const uint64_t w = (jm1 >> 6) == 0 ? k.w0 : (jm1 >> 6) == 1 ? k.w1 : k.w2;
+__device__ __forceinline__ uint32_t key_bit(const Key &k, int jm1) {
+  const uint64_t w = (jm1 >> 6) == 0 ? k.w0 : (jm1 >> 6) == 1 ? k.w1 : (jm1 >> 6) == 2 ? k.w2 : k.w3;
   return (uint32_t)((w >> (jm1 & 63)) & 1ull);
 }
 

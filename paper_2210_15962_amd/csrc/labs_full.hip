@@ -37,7 +37,7 @@ namespace full {
 
 constexpr int kG = 4;            // lanes per walk
 constexpr int kK = 3;            // top-K entries per lane
-constexpr int kRunSlots = 16;    // run table: runs, then the count in the last slot
+constexpr int kRunSlots = 32;    // run table: runs (at most 16 occur), then the count in the last slot
 
 // Lag-word class nw holds 32 nw lags, i.e. lengths up to 32 nw + 1; plane
 // counts are sized for that bound.  Word w then has |C_k| <= 32 (nw - w), so
@@ -247,7 +247,8 @@ __device__ __forceinline__ int wave_plane_cap(const uint32_t *P, bool active) {
 }
 
 // Lag words the candidates of iteration it (i = G it + 1 .. G it + G) need:
-// forward words for the smallest i, backward words for the largest.
+// forward words for the smallest i, backward words for the largest.  The
+// code is FW * 16 + BW (both at most 8).
 __host__ __device__ constexpr int words_of(int it, int L, int G, int nw) {
   const int imin = G * it + 1;
   const int imax = (G * it + G < L) ? G * it + G : L;
@@ -256,29 +257,39 @@ __host__ __device__ constexpr int words_of(int it, int L, int G, int nw) {
   fw = fw > 0 ? fw : 0;
   int bw = (imax - 1 + 31) / 32;
   bw = bw < nw ? bw : nw;
-  return fw * 8 + bw;
+  return fw * 16 + bw;
 }
 
-__host__ __device__ constexpr uint64_t words_mask(int nw, int G) {
-  uint64_t mask = 0;
+// Set of codes (0..143) as a 192-bit mask.
+struct CodeSet { uint64_t w[3]; };
+__host__ __device__ constexpr bool code_in(const CodeSet &m, int c) {
+  return c >= 0 && c < 192 && ((m.w[c >> 6] >> (c & 63)) & 1ull) != 0;
+}
+
+// Codes the candidate loop of class nw can meet (every length of the class).
+__host__ __device__ constexpr CodeSet words_mask(int nw, int G) {
+  CodeSet m{{0, 0, 0}};
   const int lo = nw == 1 ? 3 : 32 * (nw - 1) + 2;
   const int hi = (32 * nw + 1) < kFullLMax ? 32 * nw + 1 : kFullLMax;
   for (int L = lo; L <= hi; ++L)
-    for (int it = 0; it < (L + G - 1) / G; ++it) mask |= 1ull << words_of(it, L, G, nw);
-  return mask;
+    for (int it = 0; it < (L + G - 1) / G; ++it) {
+      const int c = words_of(it, L, G, nw);
+      m.w[c >> 6] |= 1ull << (c & 63);
+    }
+  return m;
 }
 
 // Calls f(FW, BW) as compile-time constants for a wave-uniform code; a code
-// outside MASK takes the all-words form, valid for every candidate.
-template <int NW, uint64_t MASK, class F>
+// outside the class's set takes the all-words form, valid for every candidate.
+template <int NW, class F>
 __device__ __forceinline__ void with_words(int code, F &&f) {
-  constexpr int kFull = NW * 8 + NW;
-  constexpr uint64_t kAll = MASK | (1ull << kFull);
-  const int eff = ((kAll >> (code & 63)) & 1ull) != 0 ? code : kFull;
-  static_for<0, 64>([&](auto cc) {
+  constexpr CodeSet kMask = words_mask(NW, kG);
+  constexpr int kFull = NW * 16 + NW;
+  const int eff = code_in(kMask, code) ? code : kFull;
+  static_for<0, 16 * NW + NW + 1>([&](auto cc) {
     constexpr int c = decltype(cc)::value;
-    constexpr int fw = c >> 3, bw = c & 7;
-    if constexpr (((kAll >> c) & 1ull) != 0 && fw <= NW && bw <= NW) {
+    constexpr int fw = c >> 4, bw = c & 15;
+    if constexpr ((code_in(kMask, c) || c == kFull) && fw <= NW && bw <= NW) {
       if (eff == c) f(std::integral_constant<int, fw>{}, std::integral_constant<int, bw>{});
     }
   });
@@ -353,7 +364,7 @@ __global__ void __launch_bounds__(kBlock) full_walk_kernel(const WalkLaunch a) {
       const int code = words_of(it, L, G, NW);
       if (code == prev) continue;
       if (n == kRunSlots - 2) {
-        runs[n - 1] = (runs[n - 1] & ~0xFFu) | (uint32_t)(NW * 8 + NW);
+        runs[n - 1] = (runs[n - 1] & ~0xFFu) | (uint32_t)(NW * 16 + NW);
         break;
       }
       runs[n++] = ((uint32_t)it << 8) | (uint32_t)code;
@@ -385,9 +396,10 @@ __global__ void __launch_bounds__(kBlock) full_walk_kernel(const WalkLaunch a) {
   constexpr int kFHI = entry_format(Gm::LMAX);
   const int efmt = entry_format(L);
   const uint32_t ev = even_c_mask(L);
+  constexpr int KWM = (Gm::LMAX + 63) / 64;        // key words any length of the class needs
 
   // ---- first pivot -----------------------------------------------------------
-  Key3 P{0, 0, 0};
+  Key P{0, 0, 0};
   if (active) {
     auto start_word = [&](int t) -> uint64_t {
       if (t >= KW) return 0ull;
@@ -404,13 +416,17 @@ __global__ void __launch_bounds__(kBlock) full_walk_kernel(const WalkLaunch a) {
     P.w0 = start_word(0);
     P.w1 = start_word(1);
     P.w2 = start_word(2);
+    P.w3 = start_word(3);
   }
+  if constexpr (KWM < 4) P.w3 = 0;
+  if constexpr (KWM < 3) P.w2 = 0;
+  if constexpr (KWM < 2) P.w1 = 0;
 
   // ---- sequence bit arrays ---------------------------------------------------
   for (int w = 0; w < 2 * Gm::NWA; ++w) colw[w * kBlock + tid] = 0u;
 #pragma unroll 1
   for (int w = 0; w < (L + 31) / 32; ++w) {
-    const uint64_t kw = (w >> 1) == 0 ? P.w0 : (w >> 1) == 1 ? P.w1 : P.w2;
+    const uint64_t kw = (w >> 1) == 0 ? P.w0 : (w >> 1) == 1 ? P.w1 : (w >> 1) == 2 ? P.w2 : P.w3;
     colw[w * kBlock + tid] = (uint32_t)(kw >> (32 * (w & 1)));
   }
 #pragma unroll 1
@@ -453,7 +469,7 @@ __global__ void __launch_bounds__(kBlock) full_walk_kernel(const WalkLaunch a) {
   });
 
   int32_t bestE = E;
-  Key3 bestP = P;
+  Key bestP = P;
   uint64_t h = 0;
   int64_t steps = 0;
   uint32_t prev_im1 = 0xFFFFFFFFu;
@@ -495,7 +511,6 @@ __global__ void __launch_bounds__(kBlock) full_walk_kernel(const WalkLaunch a) {
     }
   };
   const int nruns = (int)__builtin_amdgcn_readfirstlane(runs[kRunSlots - 1]);
-  constexpr uint64_t kMask = words_mask(NW, G);
   uint32_t ncap4 = 0u, ncap5 = 0u, ncap6 = 0u, ncap0 = 0u;
   const bool tracing = active && walk < a.n_trace;
 
@@ -512,7 +527,7 @@ __global__ void __launch_bounds__(kBlock) full_walk_kernel(const WalkLaunch a) {
     int hstat = 0;                // head: 0 unknown, 1 absent, 2 visited
     bool pstarted = false;
     uint32_t pbucket = 0, pslot = 0;   // pslot: first free entry of bucket pbucket
-    Key3 pkey{0, 0, 0};
+    Key pkey{0, 0, 0};
     bool need_scan = false;
     bool eager = true;            // probe every head in the next round
     bool done = !active;
@@ -533,7 +548,7 @@ __global__ void __launch_bounds__(kBlock) full_walk_kernel(const WalkLaunch a) {
       const uint32_t e0 = __builtin_amdgcn_readfirstlane(runs[sr]);
       const int ib = (int)(e0 >> 8);
       const int ie = (int)(__builtin_amdgcn_readfirstlane(runs[sr + 1]) >> 8);
-      with_words<NW, kMask>((int)(e0 & 0xFFu), [&](auto Fc, auto Bc) __attribute__((always_inline)) {
+      with_words<NW>((int)(e0 & 0xFFu), [&](auto Fc, auto Bc) __attribute__((always_inline)) {
         constexpr int F = decltype(Fc)::value, B = decltype(Bc)::value;
         auto scan = [&](auto BPc) __attribute__((always_inline)) {
           constexpr int BPv = decltype(BPc)::value;
@@ -579,7 +594,7 @@ __global__ void __launch_bounds__(kBlock) full_walk_kernel(const WalkLaunch a) {
           const uint32_t e0 = __builtin_amdgcn_readfirstlane(runs[sr]);
           const int ib = (int)(e0 >> 8);
           const int ie = (int)(__builtin_amdgcn_readfirstlane(runs[sr + 1]) >> 8);
-          with_words<NW, kMask>((int)(e0 & 0xFFu), [&](auto Fc, auto Bc) __attribute__((always_inline)) {
+          with_words<NW>((int)(e0 & 0xFFu), [&](auto Fc, auto Bc) __attribute__((always_inline)) {
             constexpr int F = decltype(Fc)::value, B = decltype(Bc)::value;
             uint64_t xw = ex >> ib;
 #pragma unroll 1
@@ -611,7 +626,7 @@ __global__ void __launch_bounds__(kBlock) full_walk_kernel(const WalkLaunch a) {
       const bool head_valid = !done && !lane_empty && npop < K && head != kKeyMax;
       auto probe_head = [&](uint32_t hk) {
         if (!pstarted) {
-          pkey = flip_key(P, hk & 0xFFu);
+          pkey = flip_key_n<KWM>(P, hk & 0xFFu);
           pbucket = bucket_of_hash(hP ^ zob[hk & 0xFFu], a.n_buckets);
           pstarted = true;
         }
@@ -692,7 +707,7 @@ __global__ void __launch_bounds__(kBlock) full_walk_kernel(const WalkLaunch a) {
           const int y = L - 1 - (int)im1;
           colw[(Gm::NWA + (y >> 5)) * kBlock + tid] ^= 1u << (y & 31);
         }
-        const Key3 NP = flip_key(P, im1);
+        const Key NP = flip_key_n<KWM>(P, im1);
         // the lane that probed the winner inserts it at the slot it found
         const bool owner = hstat == 1 && !lane_empty && npop < K && tk[0] == win;
         if (owner) store_entry<kFLO, kFHI>(table + (uint64_t)pbucket * kBucketBytes, pslot, NP, efmt);
@@ -727,6 +742,7 @@ __global__ void __launch_bounds__(kBlock) full_walk_kernel(const WalkLaunch a) {
     a.best_seq[walk * KW] = bestP.w0;
     if (KW > 1) a.best_seq[walk * KW + 1] = bestP.w1;
     if (KW > 2) a.best_seq[walk * KW + 2] = bestP.w2;
+    if (KW > 3) a.best_seq[walk * KW + 3] = bestP.w3;
     a.best_E[walk] = bestE;
     a.steps_done[walk] = steps;
     if (a.digest) a.digest[walk] = mix64(h ^ (uint64_t)steps);
@@ -759,6 +775,8 @@ size_t full_walk_lds_bytes(int32_t L) {
     case 4: return full::Geom<4>::lds_bytes();
     case 5: return full::Geom<5>::lds_bytes();
     case 6: return full::Geom<6>::lds_bytes();
+    case 7: return full::Geom<7>::lds_bytes();
+    case 8: return full::Geom<8>::lds_bytes();
     default: return 0;
   }
 }
@@ -772,6 +790,8 @@ hipError_t launch_full_walks(const WalkLaunch &w, hipStream_t stream) {
     case 4: return full::launch_nw<4>(w, stream);
     case 5: return full::launch_nw<5>(w, stream);
     case 6: return full::launch_nw<6>(w, stream);
+    case 7: return full::launch_nw<7>(w, stream);
+    case 8: return full::launch_nw<8>(w, stream);
     default: return hipErrorInvalidValue;
   }
 }

@@ -16,7 +16,7 @@ inline int key_words_for(int L) { return (free_bits(L) + 63) / 64; }
 inline int lag_words_for(int L) { return ((L - 1) / 2 + 31) / 32; }
 // Visited-table entry formats by key length: 12-byte entries (10 per bucket)
 // hold keys of up to 95 bits plus an occupancy flag, 16-byte entries (8 per
-// bucket) up to 127 bits, 32-byte entries (4 per bucket) up to 191 bits.
+// bucket) up to 127 bits, 32-byte entries (4 per bucket) up to 255 bits.
 enum : int { kE12 = 0, kE16 = 1, kE32 = 2 };
 __host__ __device__ constexpr int entry_format(int key_bits) {
   return key_bits <= 95 ? kE12 : key_bits <= 127 ? kE16 : kE32;
@@ -25,7 +25,7 @@ inline int entry_bytes_of(int fmt) { return fmt == kE12 ? 12 : fmt == kE16 ? 16 
 inline int entry_bytes_for(int L) { return entry_bytes_of(entry_format(free_bits(L))); }
 
 // Whole search space: keys are the L sequence bits, lags k = 1..L-1.
-constexpr int kFullLMax = 192;      // W <= 3 key words, <= 6 lag words
+constexpr int kFullLMax = 255;      // W <= 4 key words, <= 8 lag words
 inline int full_key_words_for(int L) { return (L + 63) / 64; }
 inline int full_lag_words_for(int L) { return (L - 1 + 31) / 32; }
 inline int full_entry_bytes_for(int L) { return entry_bytes_of(entry_format(L)); }

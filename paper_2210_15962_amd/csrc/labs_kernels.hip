@@ -515,7 +515,7 @@ __device__ __forceinline__ void run_block(const BlockTask &a, uint8_t *lds) {
   constexpr int KWM = (Gm::DMAX + 63) / 64;        // key words any length of the class needs
 
   // ---- first pivot P_1, or the pivot reached by an earlier launch ----------
-  Key3 P{0, 0, 0};
+  Key P{0, 0, 0};
   WalkState ws{};
   if (active && a.resume) {
     ws = a.state[walk];
@@ -596,7 +596,7 @@ __device__ __forceinline__ void run_block(const BlockTask &a, uint8_t *lds) {
   });
 
   int32_t bestE = E;
-  Key3 bestP = P;
+  Key bestP = P;
   uint64_t h = 0;
   int64_t steps = 0;
   uint32_t prev_jm1 = 0xFFFFFFFFu;
@@ -604,7 +604,7 @@ __device__ __forceinline__ void run_block(const BlockTask &a, uint8_t *lds) {
   uint8_t *table = a.tables + (uint64_t)(active ? slot : 0) * a.table_bytes;
   if (active && a.resume) {
     bestE = ws.bestE;
-    bestP = Key3{ws.bestP[0], KWM >= 2 ? ws.bestP[1] : 0ull, KWM >= 3 ? ws.bestP[2] : 0ull};
+    bestP = Key{ws.bestP[0], KWM >= 2 ? ws.bestP[1] : 0ull, KWM >= 3 ? ws.bestP[2] : 0ull};
     h = ws.h;
     steps = ws.steps;
     prev_jm1 = ws.prev_jm1;
@@ -707,7 +707,7 @@ __device__ __forceinline__ void run_block(const BlockTask &a, uint8_t *lds) {
     int hstat = 0;                // head: 0 unknown, 1 absent, 2 visited
     bool pstarted = false;
     uint32_t pbucket = 0, pslot = 0;   // pslot: first free entry of bucket pbucket
-    Key3 pkey{0, 0, 0};
+    Key pkey{0, 0, 0};
     bool need_scan = false;
     bool eager = true;            // probe every head in the next round
     bool done = !active;
@@ -902,7 +902,7 @@ __device__ __forceinline__ void run_block(const BlockTask &a, uint8_t *lds) {
           colw[(af * Gm::NWA + (rr >> 5)) * kBlock + tid] ^= 1u << (rr & 31);
           colw[((af + 2) * Gm::NWA + (rv >> 5)) * kBlock + tid] ^= 1u << (rv & 31);
         }
-        const Key3 NP = flip_key_n<KWM>(P, jm1);
+        const Key NP = flip_key_n<KWM>(P, jm1);
         // the lane that probed the winner inserts it at the slot it found
         const bool owner = hstat == 1 && !lane_empty && npop < K && tk[0] == win;
         if (owner) store_entry<kFLO, kFHI>(table + (uint64_t)pbucket * kBucketBytes, pslot, NP, efmt);

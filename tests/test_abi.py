@@ -217,10 +217,10 @@ def test_tuning_table_json_roundtrip(tmp_path):
 
 
 def test_full_space_sizes_and_validation_before_any_launch():
-    assert labs.full_l_max() == 192 and O.full_l_max() == 255
-    for L in [3, 4, 63, 64, 65, 128, 129, 192]:
+    assert labs.full_l_max() == 255 == O.full_l_max()
+    for L in [3, 4, 63, 64, 65, 128, 129, 192, 193, 247, 255]:
         assert labs.full_key_words(L) == O.full_key_words(L)
-    for bad in [-1, 0, 1, 2, 193, 383]:
+    for bad in [-1, 0, 1, 2, 256, 383]:
         assert labs.full_key_words(bad) == 0
     # 12-byte entries up to L = 95, 16-byte entries up to L = 127, then 32-byte entries
     b95 = labs.full_workspace_bytes(95, 1, 100_000)
@@ -235,7 +235,7 @@ def test_full_space_sizes_and_validation_before_any_launch():
     out = labs.WalkOut(1, 1, 1, None, None, None, 0)
     ws = ctypes.c_void_p(1)
     ref = ctypes.byref
-    for bad_L in (2, 193, -5):
+    for bad_L in (2, 256, -5):
         assert lib.labs_full_walks(None, bad_L, 4, 10, 0, ref(out), ws, 1 << 30, None, None) == labs.LABS_EINVAL
     assert lib.labs_full_walks(None, 64, -1, 10, 0, ref(out), ws, 1 << 30, None, None) == labs.LABS_EINVAL
     assert lib.labs_full_walks(None, 64, 4, -1, 0, ref(out), ws, 1 << 30, None, None) == labs.LABS_EINVAL

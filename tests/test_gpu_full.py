@@ -41,15 +41,15 @@ def _compare(L, keys, res, walk_len, n_trace=0):
         np.testing.assert_array_equal(res["trace_E"][i].cpu().numpy()[: r.steps], r.trace_E)
 
 
-LENGTHS = [3, 4, 5, 8, 13, 16, 27, 32, 33, 34, 50, 63, 64, 65, 66, 96, 97, 98, 127, 128, 129,
-           150, 160, 161, 162, 191, 192]
+LENGTHS = [3, 4, 5, 8, 13, 16, 27, 32, 33, 34, 50, 63, 64, 65, 66, 95, 96, 97, 98, 127, 128, 129,
+           150, 160, 161, 162, 191, 192, 193, 194, 200, 224, 225, 226, 247, 255]
 
 
 @pytest.mark.parametrize("L", LENGTHS)
 def test_seeded_walks_match_oracle(L):
     labs = _labs()
     n = 70                                          # two workgroups, the second ragged
-    walk_len = 400 if L <= 64 else (150 if L <= 128 else 60)
+    walk_len = 400 if L <= 64 else (150 if L <= 128 else (60 if L <= 192 else 30))
     print(f"[full] L={L} n={n} walk_len={walk_len}", flush=True)
     res = labs.full_walks(L, n, walk_len, seed=L, n_trace=2)
     torch.cuda.synchronize()
@@ -67,10 +67,10 @@ def test_trapped_walks(L):
     _compare(L, O.full_starts(L, n, 7), res, walk_len, n_trace=4)
 
 
-@pytest.mark.parametrize("L", [20, 71, 130, 192])
+@pytest.mark.parametrize("L", [20, 71, 130, 192, 247])
 def test_explicit_starts_and_chunks(L):
     labs = _labs()
-    n, walk_len = 200, 120
+    n, walk_len = 200, (120 if L <= 192 else 40)
     keys = I.random_full_keys(L, n, seed=L + 3)
     st = torch.from_numpy(I.as_int64_keys(keys)).cuda()
     res = labs.full_walks(L, n, walk_len, starts_t=st, n_trace=1)
