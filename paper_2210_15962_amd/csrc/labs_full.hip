@@ -335,8 +335,13 @@ __device__ __forceinline__ void apply_move_planes(const uint32_t *row, const uin
   });
 }
 
+// Waves per SIMD each class is built for (registers capped to fit): four up
+// to class 4 (L <= 129), three up to class 7, two for class 8.
 template <int NW>
-__global__ void __launch_bounds__(kBlock) full_walk_kernel(const WalkLaunch a) {
+struct FullOccupancy { static constexpr int value = NW <= 4 ? 4 : (NW <= 7 ? 3 : 2); };
+
+template <int NW>
+__global__ void __launch_bounds__(kBlock, FullOccupancy<NW>::value) full_walk_kernel(const WalkLaunch a) {
   using Gm = Geom<NW>;
   constexpr int G = kG, K = kK, lgG = 2;
   static_assert(G == 4, "lane index arithmetic assumes four lanes per walk");
