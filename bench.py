@@ -453,7 +453,9 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=64)
     ap.add_argument("--serve-rates", type=str, default="10,200",
                     help="arrival rates (req/s) of the serving legs in the default run")
-    ap.add_argument("--serve-chunk", type=int, default=4096)
+    ap.add_argument("--serve-chunk", type=int, default=0,
+                    help="moves per launch per request (0: launches end when a request can be "
+                         "admitted or has finished)")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--serve-sweep", type=str, default="",
                     help="comma-separated arrival rates: serve only, one JSON line per rate")

@@ -302,12 +302,17 @@ int32_t labs_autotune(int32_t L, int64_t n_walks, int64_t walk_len, void *worksp
  * and runs them with continuous batching.  A scheduler thread admits queued
  * requests first-come first-served while its device pool has room for their
  * footprint (visited tables, per-walk progress, outputs), then relaunches the
- * batch kernel over every admitted request, each launch advancing every
- * request by up to chunk_steps moves.  Walk state and visited tables stay in
- * device memory between launches; a request that arrives while others run
- * joins at the next launch; a finished request's memory is reused at once.
- * Each request's results equal a standalone labs_walks run with the same
- * (L, n_walks, walk_len, seed / starts).
+ * batch kernel over the unfinished walks of every admitted request, oldest
+ * request first.  By default (chunk_steps = 0) a launch runs until its walks
+ * finish or until the scheduler stops it, which it does as soon as a queued
+ * request can be admitted or a running request has finished: the kernel polls
+ * a stop flag in pinned host memory every 64 moves, the walks save their
+ * state, and the next launch resumes them with the newcomers.  With
+ * chunk_steps > 0 every launch instead advances each request by at most
+ * chunk_steps moves.  Walk state and visited tables stay in device memory
+ * between launches; a finished request is delivered and its memory reused at
+ * once.  Each request's results equal a standalone labs_walks run with the
+ * same (L, n_walks, walk_len, seed / starts).
  */
 typedef struct labs_server labs_server;
 
@@ -316,7 +321,8 @@ typedef struct labs_serve_cfg {
   int32_t max_pending;     /* host queue capacity; 0 = 4096 */
   int32_t lanes_per_walk;  /* 2, 4 or 8; 0 = per launch, 4 or 8, whichever fills the
                               resident workgroups in whole rounds better */
-  int64_t chunk_steps;     /* moves per launch per request; 0 = 4096 */
+  int64_t chunk_steps;     /* moves per launch per request; 0 = no limit (launches
+                              end when a request can be admitted or has finished) */
   double load_factor;      /* visited-table load factor; 0 = default 0.5 */
 } labs_serve_cfg;
 

@@ -407,9 +407,8 @@ int32_t plan_batch(const labs_instance *in, int32_t n_inst, BatchPlan &bp) {
     d.L = x.L;
     d.tables = nullptr;
     d.state = nullptr;
-    d.step_begin = 0;
+    d.wstat = nullptr;
     d.step_end = x.walk_len;
-    d.resume = 0;
     bp.inst.push_back(d);
     const int nw = lsaw::lag_words_for(x.L);
     const int per_block = lsaw::kBlock / lp.lanes_per_walk;
@@ -509,6 +508,8 @@ lsaw::BatchLaunch batch_launch(const BatchPlan &bp, uint8_t *ws, size_t k) {
   b.counter = reinterpret_cast<uint32_t *>(ws + 64 * k);      // own queue head per group
   b.arena = ws + bp.arena_off;
   b.arena_bytes = bp.arena_bytes;
+  b.preempt = nullptr;
+  b.item_done = nullptr;
   return b;
 }
 

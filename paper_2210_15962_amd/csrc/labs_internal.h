@@ -83,10 +83,10 @@ struct BatchInstanceDev {
   uint8_t *tables;          // per-walk tables (walk w at + w*table_bytes), or
                             // nullptr: the workgroup's arena, cleared per item
   WalkState *state;         // per-walk progress, or nullptr (single launch)
-  int64_t step_begin;       // moves made by every still-moving walk so far
-  int64_t step_end;         // stop when a walk has made this many moves
-  int32_t resume;           // 1: continue from state (tables already filled)
-  int32_t pad;
+  uint8_t *wstat;           // per-walk status across launches, or nullptr
+                            // (every walk starts in this launch): 0 not
+                            // started, 1 started (resume from state), 2 finished
+  int64_t step_end;         // a walk stops when it has made this many moves
   uint32_t *cap_steps;      // [n_walks][4] scans per plane cap, or nullptr
 };
 
@@ -105,6 +105,12 @@ struct BatchLaunch {
   uint32_t *counter;      // work-queue head, zeroed by launch_batch_reset
   uint8_t *arena;         // visited tables: arena_bytes per resident workgroup
   uint64_t arena_bytes;
+  // Optional (nullptr: unused).  preempt: a host word the kernel polls every
+  // 64 moves; once it is nonzero, walks save their state and no further item
+  // starts.  item_done: word i is set to 1 when item i ends with every walk
+  // finished.  Both may live in pinned host memory.
+  const uint32_t *preempt;
+  uint32_t *item_done;
 };
 
 // Host helpers shared by labs_api.cpp and labs_serve.cpp.
@@ -133,8 +139,10 @@ hipError_t launch_full_walks(const WalkLaunch &w, hipStream_t stream);
 // Batch kernel of lag-word class nw (2..6; class 1 runs on the class-2 kernel).
 int batch_variant(int nw);
 size_t batch_lds_bytes(int variant);
-hipError_t batch_blocks_per_cu(int variant, int *blocks);
+hipError_t batch_blocks_per_cu(int variant, int *blocks, bool serve = false);
 hipError_t launch_batch_reset(uint32_t *counter, hipStream_t stream);
-hipError_t launch_batch(const BatchLaunch &b, int variant, int grid, hipStream_t stream);
+// serve: the serving form (per-walk status, stop flag, item completion words).
+hipError_t launch_batch(const BatchLaunch &b, int variant, int grid, hipStream_t stream,
+                        bool serve = false);
 
 }  // namespace lsaw

@@ -450,12 +450,22 @@ struct BlockTask {
   uint64_t table_bytes;
   uint32_t n_buckets;
   WalkState *state;         // per-walk progress (indexed by walk) or nullptr
-  int64_t step_begin;       // moves every still-moving walk has made so far
+  uint8_t *wstat;           // per-walk status (batches only): 0 not started,
+                            // 1 resume from state, 2 finished; nullptr: all start
   int64_t step_end;         // moves after which this launch stops a walk
-  int32_t resume;           // continue from state: no clear, no P_1 insert
+  const uint32_t *preempt;  // batches: host stop flag polled every 64 moves, or nullptr
+  uint32_t *done_flag;      // batches: set to 1 if the block ends with every walk finished
 };
 
-template <int NW, int G, int K>
+// A nonzero stop word from the host (fine-grained memory: read past the caches).
+__device__ __forceinline__ bool stop_requested(const uint32_t *flag) {
+  const uint32_t v = __hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+  return __builtin_amdgcn_readfirstlane(v) != 0u;
+}
+
+// kSv: the serving form of the batch kernel (per-walk status, walks that
+// resume at different move counts, the host stop flag, item completion).
+template <int NW, int G, int K, bool kSv = false>
 __device__ __forceinline__ void run_block(const BlockTask &a, uint8_t *lds) {
   using Gm = Geom<NW>;
   const int Gl = (G > 0) ? G : a.lanes;        // lanes per walk (wave-uniform)
@@ -489,11 +499,21 @@ __device__ __forceinline__ void run_block(const BlockTask &a, uint8_t *lds) {
   }
   uint32_t *zob = reinterpret_cast<uint32_t *>(lds + Gm::zob_off());
   for (int j = (int)threadIdx.x; j < D; j += blockDim.x) zob[j] = zobrist_word(j);
-  if (!a.resume) {
+  const uint4 z = {0u, 0u, 0u, 0u};
+  if (kSv && a.wstat) {
+    // Walks resumed from an earlier launch keep their tables: clear only the
+    // tables of walks that start now.
+    const uint64_t n16 = a.table_bytes / 16u;
+    for (int sl = 0; sl < a.n_walks; ++sl) {
+      if (a.wstat[a.walk_begin + sl] != 0u) continue;      // uniform
+      uint4 *p = reinterpret_cast<uint4 *>(a.tables + (uint64_t)sl * a.table_bytes);
+#pragma unroll 4
+      for (uint64_t i = threadIdx.x; i < n16; i += kBlock) p[i] = z;
+    }
+  } else {
     // Clear the visited tables of this block's walks (contiguous, coalesced).
     uint4 *p = reinterpret_cast<uint4 *>(a.tables);
     const uint64_t n16 = (uint64_t)a.n_walks * (a.table_bytes / 16u);
-    const uint4 z = {0u, 0u, 0u, 0u};
 #pragma unroll 4
     for (uint64_t i = threadIdx.x; i < n16; i += kBlock) p[i] = z;
   }
@@ -504,6 +524,11 @@ __device__ __forceinline__ void run_block(const BlockTask &a, uint8_t *lds) {
   const int slot = tid / Gl;                    // walk slot inside the block
   const int64_t walk = a.walk_begin + slot;
   bool active = slot < a.n_walks;
+  // Status of the walk from earlier launches (batches with per-walk status).
+  const uint32_t wst = (kSv && a.wstat && active) ? (uint32_t)a.wstat[walk] : 0u;
+  const bool fresh = wst == 0u;                 // starts at P_1 in this launch
+  const bool skip = wst == 2u;                  // finished earlier: nothing to do
+  if (skip) active = false;
   const uint32_t colbase = (uint32_t)tid * 4u;
   uint32_t *colw = reinterpret_cast<uint32_t *>(cols);
   // Visited-table entry format of this length, within the formats the
@@ -517,7 +542,7 @@ __device__ __forceinline__ void run_block(const BlockTask &a, uint8_t *lds) {
   // ---- first pivot P_1, or the pivot reached by an earlier launch ----------
   Key P{0, 0, 0};
   WalkState ws{};
-  if (active && a.resume) {
+  if (active && !fresh) {
     ws = a.state[walk];
     P.w0 = ws.P[0];
     P.w1 = ws.P[1];
@@ -602,7 +627,7 @@ __device__ __forceinline__ void run_block(const BlockTask &a, uint8_t *lds) {
   uint32_t prev_jm1 = 0xFFFFFFFFu;
   bool trapped = false;
   uint8_t *table = a.tables + (uint64_t)(active ? slot : 0) * a.table_bytes;
-  if (active && a.resume) {
+  if (active && !fresh) {
     bestE = ws.bestE;
     bestP = Key{ws.bestP[0], KWM >= 2 ? ws.bestP[1] : 0ull, KWM >= 3 ? ws.bestP[2] : 0ull};
     h = ws.h;
@@ -618,7 +643,7 @@ __device__ __forceinline__ void run_block(const BlockTask &a, uint8_t *lds) {
   for (int jb = 0; jb < D; ++jb) hP ^= key_bit(P, jb) ? zob[jb] : 0u;
 
   // Insert P_1 (the table is empty: first entry of its home bucket).
-  if (active && !a.resume && r == 0)
+  if (active && fresh && r == 0)
     store_entry<kFLO, kFHI>(table + (uint64_t)bucket_of_hash(hP, a.n_buckets) * kBucketBytes, 0u, P, efmt);
 
   // Local candidates of lane r: j = r + 1 + Gl*i.
@@ -680,11 +705,29 @@ __device__ __forceinline__ void run_block(const BlockTask &a, uint8_t *lds) {
   };
   const bool tracing = active && walk < a.n_trace;
 
-  // Every walk still moving has made exactly step_begin moves (trapped walks
-  // are inactive), so the step counter is uniform across the workgroup.
+  // Walk kernels and plain batches: every walk starts at move 0, so the step
+  // counter is the walks' move count.  Serving: walks resumed from earlier
+  // launches may stand at different move counts (a wave can hold walks that
+  // ran in different waves before); the wave makes as many moves as its
+  // nearest-to-done walk has left, and walks still short of the end are
+  // saved unfinished and continue in the next launch.
   const int64_t step_stop = min(a.step_end, a.walk_len);
-  for (int64_t step = a.step_begin; step < step_stop; ++step) {
+  int64_t lim = step_stop;
+  if constexpr (kSv) {
+    if (steps >= step_stop) active = false;
+    int64_t rem = active ? step_stop - steps : INT64_MAX;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      const int64_t o = __shfl_xor(rem, off);
+      rem = o < rem ? o : rem;
+    }
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)(uint64_t)rem);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)rem >> 32));
+    lim = (int64_t)(((uint64_t)hi << 32) | lo);
+  }
+  for (int64_t step = 0; step < lim; ++step) {
     if (__ballot(active) == 0ull) break;
+    if (kSv && a.preempt && (step & 63) == 63 && stop_requested(a.preempt)) break;
     // Excluded local candidates (bit i <-> j = r + 1 + Gl*i): the predecessor,
     // then every candidate found visited during this step.
     uint64_t ex0 = 0ull, ex1 = 0ull, ex2 = 0ull;
@@ -919,8 +962,8 @@ __device__ __forceinline__ void run_block(const BlockTask &a, uint8_t *lds) {
         if (E < bestE) { bestE = E; bestP = P; }
         h = mix64(h ^ (((uint64_t)(jm1 + 1u) << 32) | (uint64_t)(uint32_t)E));
         if (tracing && r == 0) {
-          a.trace_j[walk * a.walk_len + step] = (int16_t)(jm1 + 1u);
-          a.trace_E[walk * a.walk_len + step] = E;
+          a.trace_j[walk * a.walk_len + steps] = (int16_t)(jm1 + 1u);
+          a.trace_E[walk * a.walk_len + steps] = E;
         }
         prev_jm1 = jm1;
         ++steps;
@@ -929,7 +972,7 @@ __device__ __forceinline__ void run_block(const BlockTask &a, uint8_t *lds) {
   }
 
   const bool finished = trapped || steps >= a.walk_len;
-  if (a.state && slot < a.n_walks && r == 0) {
+  if (a.state && slot < a.n_walks && r == 0 && !skip) {
     WalkState o{};
     o.P[0] = P.w0; o.P[1] = P.w1; o.P[2] = P.w2;
     o.bestP[0] = bestP.w0; o.bestP[1] = bestP.w1; o.bestP[2] = bestP.w2;
@@ -940,14 +983,19 @@ __device__ __forceinline__ void run_block(const BlockTask &a, uint8_t *lds) {
     o.trapped = trapped ? 1u : 0u;
     a.state[walk] = o;
   }
-  if (!trapped) write_caps();   // moved at every step of this launch
-  if (finished && slot < a.n_walks && r == 0) {
+  if (kSv && a.wstat && slot < a.n_walks && r == 0 && !skip) a.wstat[walk] = finished ? 2u : 1u;
+  if (!trapped && !skip) write_caps();   // moved at every step of this launch
+  if (finished && slot < a.n_walks && r == 0 && !skip) {
     a.best_seq[walk * KW] = bestP.w0;
     if (KW > 1) a.best_seq[walk * KW + 1] = bestP.w1;
     if (KW > 2) a.best_seq[walk * KW + 2] = bestP.w2;
     a.best_E[walk] = bestE;
     a.steps_done[walk] = steps;
     if (a.digest) a.digest[walk] = mix64(h ^ (uint64_t)steps);
+  }
+  if (kSv && a.done_flag) {
+    const int all = __syncthreads_and((slot >= a.n_walks || skip || finished) ? 1 : 0);
+    if (threadIdx.x == 0 && all) __hip_atomic_store(a.done_flag, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
   }
 }
 
@@ -975,9 +1023,10 @@ __global__ void __launch_bounds__(kBlock) walk_kernel(const WalkLaunch w) {
   t.n_buckets = w.n_buckets;
   t.cap_steps = w.cap_steps;
   t.state = nullptr;
-  t.step_begin = 0;
+  t.wstat = nullptr;
   t.step_end = w.walk_len;
-  t.resume = 0;
+  t.preempt = nullptr;
+  t.done_flag = nullptr;
   run_block<NW, G, K>(t, lds);
 }
 
@@ -992,14 +1041,17 @@ __global__ void __launch_bounds__(kBlock) walk_kernel(const WalkLaunch w) {
 template <int NWMAX>
 struct BatchOccupancy { static constexpr int value = NWMAX <= 4 ? 3 : 2; };
 
-template <int NWMAX>
+template <int NWMAX, bool kSv>
 __global__ void __launch_bounds__(kBlock, BatchOccupancy<NWMAX>::value) batch_kernel(const BatchLaunch b) {
   extern __shared__ __align__(16) uint8_t lds[];
   __shared__ int64_t s_item;
   uint8_t *arena = b.arena + (uint64_t)blockIdx.x * b.arena_bytes;
   for (;;) {
     __syncthreads();                       // previous item finished, s_item consumed
-    if (threadIdx.x == 0) s_item = (int64_t)atomicAdd(b.counter, 1u);
+    if (threadIdx.x == 0) {
+      // no further item once the host has asked the launch to stop
+      s_item = (kSv && b.preempt && stop_requested(b.preempt)) ? b.n_items : (int64_t)atomicAdd(b.counter, 1u);
+    }
     __syncthreads();
     const int64_t it = s_item;
     if (it >= b.n_items) break;            // uniform: every wave leaves together
@@ -1024,14 +1076,15 @@ __global__ void __launch_bounds__(kBlock, BatchOccupancy<NWMAX>::value) batch_ke
     t.table_bytes = in.table_bytes;
     t.n_buckets = in.n_buckets;
     t.state = in.state;
-    t.step_begin = in.step_begin;
+    t.wstat = in.wstat;
     t.step_end = in.step_end;
-    t.resume = in.resume;
+    t.preempt = b.preempt;
+    t.done_flag = b.item_done ? b.item_done + it : nullptr;
     t.lanes = item.code & 15;
     // Compiled for the largest lag-word class of the batch: shorter lengths
     // skip the unused lag words (uniform guards), lanes per walk is a runtime
     // value, so one code path serves every item.
-    run_block<NWMAX, 0, 3>(t, lds);
+    run_block<NWMAX, 0, 3, kSv>(t, lds);
   }
 }
 
@@ -1192,20 +1245,23 @@ size_t batch_lds_bytes(int variant) {
 }
 
 template <int V>
-static const void *batch_fn() { return reinterpret_cast<const void *>(batch_kernel<V>); }
+static const void *batch_fn(bool serve) {
+  return serve ? reinterpret_cast<const void *>(batch_kernel<V, true>)
+               : reinterpret_cast<const void *>(batch_kernel<V, false>);
+}
 
-static const void *batch_kernel_ptr(int variant) {
+static const void *batch_kernel_ptr(int variant, bool serve) {
   switch (variant) {
-    case 2: return batch_fn<2>();
-    case 3: return batch_fn<3>();
-    case 4: return batch_fn<4>();
-    case 5: return batch_fn<5>();
-    default: return batch_fn<6>();
+    case 2: return batch_fn<2>(serve);
+    case 3: return batch_fn<3>(serve);
+    case 4: return batch_fn<4>(serve);
+    case 5: return batch_fn<5>(serve);
+    default: return batch_fn<6>(serve);
   }
 }
 
-hipError_t batch_blocks_per_cu(int variant, int *blocks) {
-  const void *fn = batch_kernel_ptr(variant);
+hipError_t batch_blocks_per_cu(int variant, int *blocks, bool serve) {
+  const void *fn = batch_kernel_ptr(variant, serve);
   const size_t lds = batch_lds_bytes(variant);
   hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
@@ -1217,25 +1273,30 @@ hipError_t launch_batch_reset(uint32_t *counter, hipStream_t stream) {
   return hipGetLastError();
 }
 
-template <int V>
+template <int V, bool kSv>
 static hipError_t launch_batch_v(const BatchLaunch &b, int grid, hipStream_t stream) {
   const size_t lds = Geom<V>::lds_bytes();
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(batch_kernel<V>),
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(batch_kernel<V, kSv>),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(batch_kernel<V>, dim3((unsigned)grid), dim3(kBlock), lds, stream, b);
+  hipLaunchKernelGGL((batch_kernel<V, kSv>), dim3((unsigned)grid), dim3(kBlock), lds, stream, b);
   return hipGetLastError();
 }
 
-hipError_t launch_batch(const BatchLaunch &b, int variant, int grid, hipStream_t stream) {
-  if (grid <= 0) return hipSuccess;
+template <bool kSv>
+static hipError_t launch_batch_s(const BatchLaunch &b, int variant, int grid, hipStream_t stream) {
   switch (variant) {
-    case 2: return launch_batch_v<2>(b, grid, stream);
-    case 3: return launch_batch_v<3>(b, grid, stream);
-    case 4: return launch_batch_v<4>(b, grid, stream);
-    case 5: return launch_batch_v<5>(b, grid, stream);
-    default: return launch_batch_v<6>(b, grid, stream);
+    case 2: return launch_batch_v<2, kSv>(b, grid, stream);
+    case 3: return launch_batch_v<3, kSv>(b, grid, stream);
+    case 4: return launch_batch_v<4, kSv>(b, grid, stream);
+    case 5: return launch_batch_v<5, kSv>(b, grid, stream);
+    default: return launch_batch_v<6, kSv>(b, grid, stream);
   }
+}
+
+hipError_t launch_batch(const BatchLaunch &b, int variant, int grid, hipStream_t stream, bool serve) {
+  if (grid <= 0) return hipSuccess;
+  return serve ? launch_batch_s<true>(b, variant, grid, stream) : launch_batch_s<false>(b, variant, grid, stream);
 }
 
 }  // namespace lsaw

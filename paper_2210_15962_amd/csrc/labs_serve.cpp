@@ -2,12 +2,16 @@
 //
 // A scheduler thread owns a device memory pool.  Requests (one walk job of
 // any L each) wait in a FIFO host queue; the head is admitted as soon as its
-// footprint fits a free range of the pool.  Every admitted request is advanced
-// by up to chunk_steps moves per launch of the persistent batch kernel, with
-// each walk's progress and visited table kept in the pool between launches,
-// so requests that arrive while others run join at the next launch and their
-// work overlaps on the device.  Completed requests are copied to host memory
-// and their pool range is freed immediately.
+// footprint fits a free range of the pool.  Each launch of the persistent
+// batch kernel runs every admitted request's unfinished walks, oldest request
+// first; each walk's progress and visited table stay in the pool between
+// launches.  By default a launch runs until its walks finish or until the
+// scheduler asks it to stop (a host flag the kernel polls every 64 moves)
+// because a queued request can be admitted or a running one has finished;
+// the walks then save their state and the next launch, with the newcomers,
+// resumes them.  With chunk_steps set, a launch advances every request by at
+// most chunk_steps moves instead.  Completed requests are copied to host
+// memory and their pool range is freed immediately.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 #include <string.h>
@@ -77,6 +81,12 @@ class RangeAlloc {
       }
     }
   }
+  bool fits(uint64_t bytes) const {
+    bytes = al(bytes);
+    for (const auto &kv : free_)
+      if (kv.second >= bytes) return true;
+    return false;
+  }
   uint64_t used() const { return used_; }
   uint64_t peak() const { return peak_; }
 
@@ -99,9 +109,12 @@ struct Request {
   int W;
   // pool range and the buffers inside it
   uint64_t off = 0, bytes = 0;
-  uint64_t o_tables = 0, o_state = 0, o_starts = 0, o_seq = 0, o_E = 0, o_steps = 0, o_dig = 0;
-  int64_t progress = 0;           // moves every still-moving walk has made
+  uint64_t o_tables = 0, o_state = 0, o_wstat = 0, o_starts = 0, o_seq = 0, o_E = 0, o_steps = 0,
+           o_dig = 0;
+  int64_t progress = 0;           // chunked launches: moves every still-moving walk has made
   bool launched = false;
+  std::vector<uint8_t> walk_done; // walks known finished (host view)
+  int64_t n_done = 0;
   bool upload = false;
   int status = ST_PENDING;
   int64_t t_submit = 0, t_admit = 0, t_done = 0;
@@ -115,6 +128,9 @@ constexpr int kMaxItems = 1 << 17;
 // the work list and the instance table of the current launch.
 constexpr uint64_t kCtlHead = 512;
 constexpr int kMaxInst = 8192;
+// Pinned host words the kernel reads and writes: the stop flag, then one
+// completion word per work item of the current launch.
+constexpr int kHostFlagWords = 64;
 
 }  // namespace
 
@@ -127,7 +143,9 @@ struct labs_server {
   uint64_t ctl_bytes = 0;           // control region size
   int32_t max_pending = 4096;
   int32_t lanes = 0;
-  int64_t chunk = 8192;
+  int64_t chunk = 0;                // moves per launch; 0: run until done or asked to stop
+  uint32_t *host_words = nullptr;   // pinned: stop flag, then item completion words
+  uint32_t *dev_words = nullptr;    // the same memory as the kernel addresses it
   double load_factor = 0.5;
   std::mutex mu;
   std::condition_variable cv_work, cv_done;
@@ -148,6 +166,7 @@ uint64_t footprint(Request &q) {
   uint64_t o = 0;
   q.o_tables = o; o += al((uint64_t)q.n_walks * q.table_bytes);
   q.o_state = o; o += al((uint64_t)q.n_walks * sizeof(lsaw::WalkState));
+  q.o_wstat = o; o += al((uint64_t)q.n_walks);
   q.o_starts = o; o += q.starts.empty() ? 0 : al((uint64_t)q.n_walks * q.W * 8);
   q.o_seq = o; o += al((uint64_t)q.n_walks * q.W * 8);
   q.o_E = o; o += al((uint64_t)q.n_walks * 4);
@@ -175,11 +194,28 @@ hipError_t finish(labs_server *s, Request *q) {
   return e;
 }
 
+// Groups of `per` walks of q that still have an unfinished walk.
+int64_t groups_left(const Request &q, int per) {
+  int64_t n = 0;
+  for (int64_t w = 0; w < q.n_walks; w += per) {
+    const int64_t e = std::min<int64_t>(w + per, q.n_walks);
+    for (int64_t x = w; x < e; ++x)
+      if (!q.walk_done[(size_t)x]) {
+        ++n;
+        break;
+      }
+  }
+  return n;
+}
+
 void run_worker(labs_server *s) {
   (void)hipSetDevice(s->device);
   std::vector<lsaw::BatchInstanceDev> inst;
   std::vector<lsaw::BatchItemDev> items;
   std::vector<int64_t> budget;
+  volatile uint32_t *stop_flag = s->host_words;
+  volatile uint32_t *item_done = s->host_words + kHostFlagWords;
+  const bool preemptive = s->chunk == 0;
   for (;;) {
     std::vector<Request *> run;
     {
@@ -196,6 +232,7 @@ void run_worker(labs_server *s) {
         q->status = ST_ACTIVE;
         q->t_admit = now_ns();
         q->upload = !q->starts.empty();
+        q->walk_done.assign((size_t)q->n_walks, 0);
         s->pending.pop_front();
         s->active.push_back(q);
         n_items += items_of(*q, 8);
@@ -228,7 +265,7 @@ void run_worker(labs_server *s) {
       for (int v = 6; v >= 2; --v) {
         if (!present[v]) continue;
         int occ = 0;
-        if (lsaw::batch_blocks_per_cu(v, &occ) != hipSuccess) occ = 0;
+        if (lsaw::batch_blocks_per_cu(v, &occ, true) != hipSuccess) occ = 0;
         if (top && occ <= top_occ) {
           launch_v[v] = top;
         } else {
@@ -240,24 +277,31 @@ void run_worker(labs_server *s) {
     auto class_launch = [&](int L) { return launch_v[lsaw::batch_variant(lsaw::lag_words_for(L))]; };
     int64_t slots_v[8] = {0}, items4_v[8] = {0};
     int lanes_v[8] = {4, 4, 4, 4, 4, 4, 4, 4};
-    for (Request *q : run) items4_v[class_launch(q->L)] += items_of(*q, 4);
+    for (Request *q : run) items4_v[class_launch(q->L)] += groups_left(*q, lsaw::kBlock / 4);
     for (int v = 2; v <= 6; ++v) {
       if (!items4_v[v]) continue;
       int per_cu = 1;
-      (void)lsaw::batch_blocks_per_cu(v, &per_cu);
+      (void)lsaw::batch_blocks_per_cu(v, &per_cu, true);
       slots_v[v] = (int64_t)std::max(per_cu, 1) * cus;
       // Lanes per walk for this launch (walk state and tables do not depend
-      // on it): a request's own choice if it has one, else 4 or 8, whichever
-      // fills the class's resident workgroups in whole rounds better (8 lanes
-      // cost about 20% more per walk step than 4: the per-move work is shared
-      // by half as many candidates per lane).
-      auto fill = [&](int64_t n) {
-        const int64_t rounds = (n + slots_v[v] - 1) / slots_v[v];
-        return rounds > 0 ? (double)n / (double)(rounds * slots_v[v]) : 0.0;
-      };
-      lanes_v[v] = 0.8 * fill(2 * items4_v[v]) > fill(items4_v[v]) ? 8 : 4;
+      // on it): a request's own choice if it has one, else 4 or 8.  Eight
+      // lanes cost about 20% more per walk step than four (the per-move work
+      // is shared by half as many candidates per lane), so they pay only
+      // where four leave resident workgroups idle.  Chunked launches run
+      // every item to the chunk's end, so what counts there is how well the
+      // items fill whole rounds of workgroups; launches that are stopped
+      // early keep every workgroup busy once the items outnumber them.
+      if (preemptive) {
+        lanes_v[v] = 6 * items4_v[v] < 5 * slots_v[v] ? 8 : 4;
+      } else {
+        auto fill = [&](int64_t n) {
+          const int64_t rounds = (n + slots_v[v] - 1) / slots_v[v];
+          return rounds > 0 ? (double)n / (double)(rounds * slots_v[v]) : 0.0;
+        };
+        lanes_v[v] = 0.8 * fill(2 * items4_v[v]) > fill(items4_v[v]) ? 8 : 4;
+      }
     }
-    hipError_t up_err = hipSuccess;           // first failing starts upload, if any
+    hipError_t up_err = hipSuccess;           // first failing upload or clear, if any
     for (size_t k = 0; k < run.size(); ++k) {
       Request *q = run[k];
       uint8_t *b = s->pool + s->ctl_bytes + q->off;
@@ -267,7 +311,9 @@ void run_worker(labs_server *s) {
                                   hipMemcpyHostToDevice, s->stream);
         q->upload = false;
       }
-      const int64_t take = std::min(s->chunk, q->walk_len - q->progress);
+      if (!q->launched && up_err == hipSuccess)   // every walk starts "not started"
+        up_err = hipMemsetAsync(b + q->o_wstat, 0, (size_t)q->n_walks, s->stream);
+      const int64_t take = preemptive ? q->walk_len : std::min(s->chunk, q->walk_len - q->progress);
       budget.push_back(take);
       lsaw::BatchInstanceDev d{};
       d.starts = q->starts.empty() ? nullptr : reinterpret_cast<const uint64_t *>(b + q->o_starts);
@@ -285,28 +331,32 @@ void run_worker(labs_server *s) {
       d.L = q->L;
       d.tables = b + q->o_tables;
       d.state = reinterpret_cast<lsaw::WalkState *>(b + q->o_state);
-      d.step_begin = q->progress;
-      d.step_end = q->progress + take;
-      d.resume = q->launched ? 1 : 0;
+      d.wstat = b + q->o_wstat;
+      d.step_end = preemptive ? q->walk_len : q->progress + take;
       inst.push_back(d);
       const int lanes = q->lanes ? q->lanes : lanes_v[class_launch(q->L)];
       const int per = lsaw::kBlock / lanes;
       for (int64_t w = 0; w < q->n_walks; w += per) {
+        const int64_t n = std::min<int64_t>(per, q->n_walks - w);
+        bool left = false;
+        for (int64_t x = w; x < w + n && !left; ++x) left = !q->walk_done[(size_t)x];
+        if (!left) continue;                  // every walk of the group has finished
         lsaw::BatchItemDev it{};
         it.inst = (int32_t)k;
         it.code = (lsaw::lag_words_for(q->L) << 4) | lanes;
-        it.n_walks = (int32_t)std::min<int64_t>(per, q->n_walks - w);
+        it.n_walks = (int32_t)n;
         it.walk_begin = w;
         items.push_back(it);
       }
     }
-    // by class, then longest items first (cost grows with L) so that each
-    // persistent grid ends on short items
+    // By class; then, in chunked launches, longest items first (cost grows
+    // with L, so each persistent grid ends on short items), else oldest
+    // request first (launches are cut short, so no grid tail to shape).
     auto variant_of = [&](const lsaw::BatchItemDev &x) { return class_launch(inst[x.inst].L); };
     std::stable_sort(items.begin(), items.end(), [&](const lsaw::BatchItemDev &x, const lsaw::BatchItemDev &y) {
       const int vx = variant_of(x), vy = variant_of(y);
       if (vx != vy) return vx > vy;
-      return inst[x.inst].L > inst[y.inst].L;
+      return preemptive ? x.inst < y.inst : inst[x.inst].L > inst[y.inst].L;
     });
     uint8_t *ctl = s->pool;
     const uint64_t items_off = kCtlHead;
@@ -318,6 +368,11 @@ void run_worker(labs_server *s) {
     bl.counter = reinterpret_cast<uint32_t *>(ctl);
     bl.arena = nullptr;                       // every instance brings its own tables
     bl.arena_bytes = 0;
+    bl.preempt = preemptive ? s->dev_words : nullptr;
+    bl.item_done = s->dev_words + kHostFlagWords;
+    // No kernel runs now: the flag and the completion words can be reset.
+    *stop_flag = 0u;
+    for (size_t i = 0; i < items.size(); ++i) item_done[i] = 0u;
     const int64_t t0 = now_ns();
     hipError_t e = up_err;
     if (e == hipSuccess)
@@ -327,6 +382,7 @@ void run_worker(labs_server *s) {
       e = hipMemcpyAsync(ctl + inst_off, inst.data(), inst.size() * sizeof(lsaw::BatchInstanceDev),
                          hipMemcpyHostToDevice, s->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(s->stream);   // work lists in place
+    bool used_v[8] = {false};
     for (size_t g0 = 0; g0 < items.size() && e == hipSuccess;) {
       const int v = variant_of(items[g0]);
       size_t g1 = g0;
@@ -334,6 +390,7 @@ void run_worker(labs_server *s) {
       lsaw::BatchLaunch bg = bl;
       bg.items = bl.items + g0;
       bg.n_items = (int64_t)(g1 - g0);
+      bg.item_done = bl.item_done + g0;
       const int grid = (int)std::min<int64_t>(bg.n_items, slots_v[v]);
       // Groups hold disjoint requests, so they run concurrently, each on its
       // own stream with its own queue head: one group's tail overlaps the
@@ -341,18 +398,68 @@ void run_worker(labs_server *s) {
       // grids finish whatever share of the GPU each gets.
       bg.counter = reinterpret_cast<uint32_t *>(ctl) + 16 * v;
       e = lsaw::launch_batch_reset(bg.counter, s->group_stream[v]);
-      if (e == hipSuccess) e = lsaw::launch_batch(bg, v, grid, s->group_stream[v]);
+      if (e == hipSuccess) e = lsaw::launch_batch(bg, v, grid, s->group_stream[v], true);
+      used_v[v] = true;
       g0 = g1;
     }
+    if (preemptive && e == hipSuccess) {
+      // Let the launch run until its walks finish, or ask it to stop (it then
+      // ends within about 64 moves per walk) once a queued request can be
+      // admitted, a running request has finished (so that it is delivered and
+      // its memory freed now), or the server shuts down.
+      bool asked = false;
+      int64_t t_check = 0;
+      std::vector<int64_t> left(run.size(), 0);
+      for (;;) {
+        bool busy = false;
+        for (int v = 2; v <= 6 && e == hipSuccess; ++v) {
+          if (!used_v[v]) continue;
+          const hipError_t qe = hipStreamQuery(s->group_stream[v]);
+          if (qe == hipErrorNotReady) busy = true;
+          else if (qe != hipSuccess) e = qe;
+        }
+        if (!busy || e != hipSuccess) break;
+        if (!asked) {
+          bool want = false;
+          const int64_t t = now_ns();
+          if (t - t_check > 2000000) {            // scan the completion words every 2 ms
+            t_check = t;
+            std::fill(left.begin(), left.end(), 0);
+            for (size_t i = 0; i < items.size(); ++i)
+              if (!item_done[i]) left[(size_t)items[i].inst]++;
+            for (size_t k = 0; k < run.size() && !want; ++k) want = left[k] == 0;
+          }
+          std::unique_lock<std::mutex> lk(s->mu);
+          want = want || s->stop || (!s->pending.empty() && s->ranges.fits(s->pending.front()->bytes));
+          if (want) {
+            *stop_flag = 1u;
+            asked = true;
+          } else {
+            s->cv_work.wait_for(lk, std::chrono::microseconds(200));
+          }
+        }
+        if (asked) std::this_thread::sleep_for(std::chrono::microseconds(100));
+      }
+    }
     for (int v = 2; v <= 6; ++v)
-      if (e == hipSuccess) e = hipStreamSynchronize(s->group_stream[v]);
+      if (used_v[v] && e == hipSuccess) e = hipStreamSynchronize(s->group_stream[v]);
     const int64_t t1 = now_ns();
+    // Items that ended with every walk finished, from the completion words.
+    for (size_t i = 0; i < items.size() && e == hipSuccess; ++i) {
+      if (!item_done[i]) continue;
+      Request *q = run[(size_t)items[i].inst];
+      for (int64_t x = items[i].walk_begin; x < items[i].walk_begin + items[i].n_walks; ++x)
+        if (!q->walk_done[(size_t)x]) {
+          q->walk_done[(size_t)x] = 1;
+          q->n_done++;
+        }
+    }
     std::vector<Request *> done;
     for (size_t k = 0; k < run.size() && e == hipSuccess; ++k) {
       Request *q = run[k];
       q->launched = true;
-      q->progress += budget[k];
-      if (q->progress >= q->walk_len) {
+      if (!preemptive) q->progress += budget[k];
+      if (q->n_done == q->n_walks) {
         e = finish(s, q);
         done.push_back(q);
       }
@@ -421,7 +528,7 @@ int32_t labs_serve_create(const labs_serve_cfg *cfg, labs_server **server) {
   labs_server *s = new labs_server();
   s->max_pending = c.max_pending ? c.max_pending : 4096;
   s->lanes = c.lanes_per_walk;
-  s->chunk = c.chunk_steps ? c.chunk_steps : 4096;
+  s->chunk = c.chunk_steps;
   s->load_factor = c.load_factor != 0.0 ? c.load_factor : 0.0;
   hipError_t e = hipGetDevice(&s->device);
   size_t free_b = 0, total_b = 0;
@@ -432,6 +539,14 @@ int32_t labs_serve_create(const labs_serve_cfg *cfg, labs_server **server) {
   want = al(want);
   if (e == hipSuccess && want <= s->ctl_bytes) e = hipErrorInvalidValue;
   if (e == hipSuccess) e = hipMalloc(&s->pool, want);
+  // Coherent pinned words: the scheduler raises the stop flag while a launch
+  // runs and reads the kernel's item completion words.
+  if (e == hipSuccess)
+    e = hipHostMalloc(reinterpret_cast<void **>(&s->host_words),
+                      (size_t)(kHostFlagWords + kMaxItems) * sizeof(uint32_t),
+                      hipHostMallocMapped | hipHostMallocCoherent);
+  if (e == hipSuccess)
+    e = hipHostGetDevicePointer(reinterpret_cast<void **>(&s->dev_words), s->host_words, 0);
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking);
   for (int v = 2; v <= 6 && e == hipSuccess; ++v)
     e = hipStreamCreateWithFlags(&s->group_stream[v], hipStreamNonBlocking);
@@ -440,6 +555,7 @@ int32_t labs_serve_create(const labs_serve_cfg *cfg, labs_server **server) {
     for (int v = 2; v <= 6; ++v)
       if (s->group_stream[v]) (void)hipStreamDestroy(s->group_stream[v]);
     if (s->pool) (void)hipFree(s->pool);
+    if (s->host_words) (void)hipHostFree(s->host_words);
     delete s;
     return lsaw::set_error(e == hipErrorOutOfMemory ? LABS_ENOMEM : LABS_EDEVICE, "serve create: %s",
                            hipGetErrorString(e));
@@ -465,6 +581,7 @@ int32_t labs_serve_destroy(labs_server *s) {
   for (int v = 2; v <= 6; ++v)
     if (s->group_stream[v]) (void)hipStreamDestroy(s->group_stream[v]);
   if (s->pool) (void)hipFree(s->pool);
+  if (s->host_words) (void)hipHostFree(s->host_words);
   delete s;
   return lsaw::clear_error();
 }

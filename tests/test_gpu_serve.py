@@ -43,7 +43,10 @@ def _assert_same(served, alone):
     np.testing.assert_array_equal(served["steps_done"], alone["steps_done"])
 
 
-def test_mix_equals_alone_and_oracle():
+@pytest.mark.parametrize("chunk", [700, 0])
+def test_mix_equals_alone_and_oracle(chunk):
+    """chunk 700: every launch advances each request by at most 700 moves;
+    chunk 0: launches run until a request can be admitted or has finished."""
     labs = _labs()
     Ls = [int(x) for x in I.odd_lengths(6, 121, 301, seed=21)] + [7, 27]
     reqs = [dict(L=L, n=[128, 300, 64, 257][i % 4], walk_len=[3000, 2500, 1800][i % 3], seed=50 + i)
@@ -51,7 +54,7 @@ def test_mix_equals_alone_and_oracle():
     reqs.append(dict(L=27, n=16, walk_len=0, seed=3))                  # nothing to walk
     keys = I.random_start_keys(151, 40, seed=8)
     reqs.append(dict(L=151, n=40, walk_len=2222, seed=0, starts=keys))
-    with labs.Server(pool_bytes=POOL, chunk_steps=700) as srv:
+    with labs.Server(pool_bytes=POOL, chunk_steps=chunk) as srv:
         ids = []
         for i, q in enumerate(reqs):
             ids.append(srv.submit(q["L"], q["n"], q["walk_len"], q["seed"], q.get("starts")))
@@ -74,15 +77,20 @@ def test_mix_equals_alone_and_oracle():
             assert r["steps_done"][i] == o.steps
     assert st["submitted"] == st["admitted"] == st["completed"] == len(reqs)
     assert st["pending"] == 0 and st["active"] == 0 and st["pool_used"] == 0
-    assert st["launches"] >= 5                                         # 3000 moves / 700 per launch
+    if chunk:
+        assert st["launches"] >= 5                                     # 3000 moves / 700 per launch
+    else:
+        assert st["launches"] >= 2                                     # spread arrivals stop launches
     assert st["walk_steps"] == sum(r["total_steps"] for r in out)
     assert 0 < st["pool_peak"] <= st["pool_bytes"]
 
 
-def test_late_arrival_joins_running_request():
-    """A short request submitted while a long one runs finishes first."""
+@pytest.mark.parametrize("chunk", [1024, 0])
+def test_late_arrival_joins_running_request(chunk):
+    """A short request submitted while a long one runs finishes first (with
+    chunk 0 its arrival stops the running launch, and so does its completion)."""
     labs = _labs()
-    with labs.Server(pool_bytes=POOL, chunk_steps=1024) as srv:
+    with labs.Server(pool_bytes=POOL, chunk_steps=chunk) as srv:
         a = srv.submit(201, 256, 40000, seed=1)
         while srv.stats()["admitted"] < 1:
             time.sleep(0.001)
@@ -90,6 +98,9 @@ def test_late_arrival_joins_running_request():
         b = srv.submit(161, 64, 2048, seed=2)
         rb = srv.wait(b, timeout_s=120)
         ra = srv.wait(a, timeout_s=120)
+        st = srv.stats()
+    if not chunk:
+        assert st["launches"] >= 3          # a alone, a + b until b finishes, the rest of a
     assert rb["t_done_ns"] < ra["t_done_ns"]
     assert rb["t_admit_ns"] < ra["t_done_ns"]
     _assert_same(rb, _standalone(161, 64, 2048, 2))
@@ -127,6 +138,30 @@ def test_admission_waits_for_memory_and_queue_limit():
         assert srv.stats()["pool_peak"] == fp
     _assert_same(ra, alone)
     _assert_same(rb, _standalone(L, n, wl, 6))
+
+
+def test_finished_request_frees_memory_for_the_queue():
+    """Default launches: a pool that holds two of these requests (equal
+    footprints: same walk_len, key words and entry size) and a queue of two.
+    The short-L request finishes first; its completion stops the launch, so
+    the third request is admitted while the first still runs.  Every result
+    equals its standalone run."""
+    labs = _labs()
+    Ls, n, wl = [189, 131, 187, 133], 64, 6000
+    with labs.Server(pool_bytes=POOL, load_factor=0.5) as probe:
+        probe.wait(probe.submit(Ls[0], n, wl, seed=0), timeout_s=120)
+        st = probe.stats()
+        fp, ctl = st["pool_peak"], POOL - st["pool_bytes"]
+    with labs.Server(pool_bytes=ctl + 2 * fp + fp // 2, load_factor=0.5) as srv:
+        ids = [srv.submit(L, n, wl, seed=30 + i) for i, L in enumerate(Ls)]
+        out = [srv.wait(rid, timeout_s=120) for rid in ids]
+        st = srv.stats()
+    for i, (L, r) in enumerate(zip(Ls, out)):
+        _assert_same(r, _standalone(L, n, wl, 30 + i))
+    assert st["completed"] == len(Ls) and st["pool_used"] == 0
+    assert st["pool_peak"] == 2 * fp
+    assert out[1]["t_done_ns"] < out[0]["t_done_ns"]
+    assert out[1]["t_done_ns"] <= out[2]["t_admit_ns"] < out[0]["t_done_ns"]
 
 
 def test_poll_wait_timeout_and_unknown_ids():
