@@ -265,6 +265,23 @@ int32_t labs_walks_batch(const labs_instance *inst, int32_t n_inst, void *worksp
                          uint64_t ws_bytes, void *stream);
 
 /*
+ * Whole-space batches (Sec. 5's sokol_full, see labs_full_walks): instances of
+ * any L in [3, 255], each one labs_full_walks job (lanes_per_walk 0 or 4,
+ * load_factor 0 = 0.5), run the way labs_walks_batch runs skew-symmetric
+ * instances: persistent launches, one per group of lag-word classes (classes
+ * 1-4, 5-7 and 8, i.e. L <= 129, L <= 225 and above), draining a work queue of
+ * (instance, block of 64 walks) items, longest L first.  Workspace, streams
+ * and the work-list upload behave as for labs_batch_workspace_bytes and
+ * labs_walks_batch.  Results are identical to running each instance alone
+ * with labs_full_walks.
+ * Errors: LABS_EINVAL (any invalid instance, workspace below one arena),
+ * LABS_EDEVICE.
+ */
+int32_t labs_full_batch_workspace_bytes(const labs_instance *inst, int32_t n_inst, uint64_t *bytes);
+int32_t labs_full_walks_batch(const labs_instance *inst, int32_t n_inst, void *workspace,
+                              uint64_t ws_bytes, void *stream);
+
+/*
  * hipGraph form of labs_walks_batch: create uploads the work items once and
  * captures the queue reset and the persistent launch into an executable
  * graph; launch replays it on `stream` (each replay recomputes the same

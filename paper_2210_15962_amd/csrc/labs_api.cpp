@@ -353,6 +353,7 @@ struct BatchGroup {
 };
 
 struct BatchPlan {
+  bool full = false;                         // whole-space instances (labs_full_walks_batch)
   std::vector<lsaw::BatchInstanceDev> inst;
   std::vector<lsaw::BatchItemDev> items;
   std::vector<BatchGroup> groups;            // one persistent launch each, in order
@@ -362,9 +363,10 @@ struct BatchPlan {
 
 uint64_t align256(uint64_t x) { return (x + 255) & ~(uint64_t)255; }
 
-int32_t plan_batch(const labs_instance *in, int32_t n_inst, BatchPlan &bp) {
+int32_t plan_batch(const labs_instance *in, int32_t n_inst, BatchPlan &bp, bool full = false) {
   if (n_inst < 0) return fail(LABS_EINVAL, "n_inst must be >= 0");
   if (n_inst > 0 && !in) return fail(LABS_EINVAL, "NULL instance array");
+  bp.full = full;
   bp.inst.clear();
   bp.items.clear();
   bp.groups.clear();
@@ -374,15 +376,22 @@ int32_t plan_batch(const labs_instance *in, int32_t n_inst, BatchPlan &bp) {
   for (int32_t i = 0; i < n_inst; ++i) {
     const labs_instance &x = in[i];
     labs_plan lp{x.lanes_per_walk, x.load_factor, 0};
-    const Tuned tu = tuned_for(x.L);
-    if (lp.lanes_per_walk == 0) lp.lanes_per_walk = tu.lanes;
-    if (lp.load_factor == 0.0) lp.load_factor = tu.load_factor;
-    if (lp.lanes_per_walk != 2 && lp.lanes_per_walk != 4 && lp.lanes_per_walk != 8)
-      return fail(LABS_EINVAL, "instance %d: lanes_per_walk %d (batches use 2, 4 or 8)", i,
-                  lp.lanes_per_walk);
     Plan p;
-    int32_t rc = make_plan(x.L, x.walk_len, &lp, p);
-    if (rc != LABS_OK) return fail(rc, "instance %d: %s", i, g_err.c_str());
+    if (full) {
+      // whole space: four lanes per walk, load factor as given or 0.5
+      int32_t rc = make_full_plan(x.L, x.walk_len, &lp, p);
+      if (rc != LABS_OK) return fail(rc, "instance %d: %s", i, g_err.c_str());
+      lp.lanes_per_walk = p.G;
+    } else {
+      const Tuned tu = tuned_for(x.L);
+      if (lp.lanes_per_walk == 0) lp.lanes_per_walk = tu.lanes;
+      if (lp.load_factor == 0.0) lp.load_factor = tu.load_factor;
+      if (lp.lanes_per_walk != 2 && lp.lanes_per_walk != 4 && lp.lanes_per_walk != 8)
+        return fail(LABS_EINVAL, "instance %d: lanes_per_walk %d (batches use 2, 4 or 8)", i,
+                    lp.lanes_per_walk);
+      int32_t rc = make_plan(x.L, x.walk_len, &lp, p);
+      if (rc != LABS_OK) return fail(rc, "instance %d: %s", i, g_err.c_str());
+    }
     if (x.n_walks < 0) return fail(LABS_EINVAL, "instance %d: n_walks < 0", i);
     if (x.n_walks > 0 && (!x.out.best_seq || !x.out.best_E || !x.out.steps_done))
       return fail(LABS_EINVAL, "instance %d: best_seq, best_E and steps_done are required", i);
@@ -410,15 +419,17 @@ int32_t plan_batch(const labs_instance *in, int32_t n_inst, BatchPlan &bp) {
     d.wstat = nullptr;
     d.step_end = x.walk_len;
     bp.inst.push_back(d);
-    const int nw = lsaw::lag_words_for(x.L);
     const int per_block = lsaw::kBlock / lp.lanes_per_walk;
     bp.arena_bytes = std::max(bp.arena_bytes, (uint64_t)per_block * p.table_bytes);
-    order.push_back(Ord{lsaw::batch_variant(nw), lp.lanes_per_walk, x.L, i});
+    const int variant = full ? lsaw::full_batch_variant(lsaw::full_lag_words_for(x.L))
+                             : lsaw::batch_variant(lsaw::lag_words_for(x.L));
+    order.push_back(Ord{variant, lp.lanes_per_walk, x.L, i});
   }
   // Classes whose kernels reach the same occupancy share one launch on the
   // largest class's kernel (a shorter length runs on a longer class's kernel
-  // exactly): separate launches would only add tails.
-  {
+  // exactly): separate launches would only add tails.  (The whole-space
+  // kernel groups are formed that way already.)
+  if (!full) {
     int present[8] = {0};
     for (const Ord &o : order) present[o.variant] = 1;
     int merged[8] = {0, 0, 2, 3, 4, 5, 6, 6};
@@ -452,7 +463,7 @@ int32_t plan_batch(const labs_instance *in, int32_t n_inst, BatchPlan &bp) {
     for (int64_t b = 0; b < n; b += per_block) {
       lsaw::BatchItemDev it{};
       it.inst = o.idx;
-      it.code = (lsaw::lag_words_for(in[o.idx].L) << 4) | o.G;
+      it.code = ((full ? lsaw::full_lag_words_for(in[o.idx].L) : lsaw::lag_words_for(in[o.idx].L)) << 4) | o.G;
       it.n_walks = (int32_t)std::min<int64_t>(per_block, n - b);
       it.walk_begin = b;
       bp.items.push_back(it);
@@ -465,11 +476,12 @@ int32_t plan_batch(const labs_instance *in, int32_t n_inst, BatchPlan &bp) {
   return LABS_OK;
 }
 
-int32_t device_resident_blocks(int variant, int64_t *blocks) {
+int32_t device_resident_blocks(int variant, bool full, int64_t *blocks) {
   int dev = 0, cus = 0, per_cu = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-  if (e == hipSuccess) e = lsaw::batch_blocks_per_cu(variant, &per_cu);
+  if (e == hipSuccess)
+    e = full ? lsaw::full_batch_blocks_per_cu(variant, &per_cu) : lsaw::batch_blocks_per_cu(variant, &per_cu);
   if (e != hipSuccess) return fail(LABS_EDEVICE, "device query: %s", hipGetErrorString(e));
   *blocks = (int64_t)std::max(1, per_cu) * (int64_t)cus;
   return LABS_OK;
@@ -488,7 +500,7 @@ int32_t batch_grids(const BatchPlan &bp, uint64_t ws_bytes, std::vector<int> &gr
   uint64_t total = 0;
   for (const BatchGroup &grp : bp.groups) {
     int64_t resident = 0;
-    int32_t rc = device_resident_blocks(grp.variant, &resident);
+    int32_t rc = device_resident_blocks(grp.variant, bp.full, &resident);
     if (rc != LABS_OK) return rc;
     grids.push_back((int)std::min<int64_t>(grp.count, resident));
     total += (uint64_t)grids.back();
@@ -541,6 +553,12 @@ hipError_t side_streams(SideStreams **out) {
   return hipSuccess;
 }
 
+hipError_t launch_group(const BatchPlan &bp, const lsaw::BatchLaunch &b, size_t k, int grid,
+                        hipStream_t st) {
+  return bp.full ? lsaw::launch_full_batch(b, bp.groups[k].variant, grid, st)
+                 : lsaw::launch_batch(b, bp.groups[k].variant, grid, st);
+}
+
 // Enqueue every group of a batch on `st`.  Concurrent: group 0 on st itself,
 // the others forked onto side streams and joined back, each on its own range
 // of arena slices (one group's tail overlaps another's work).  Otherwise the
@@ -554,7 +572,7 @@ hipError_t enqueue_groups(const BatchPlan &bp, uint8_t *ws, const std::vector<in
     for (size_t k = 0; k < bp.groups.size() && e == hipSuccess; ++k) {
       lsaw::BatchLaunch b = batch_launch(bp, ws, k);
       e = lsaw::launch_batch_reset(b.counter, st);
-      if (e == hipSuccess) e = lsaw::launch_batch(b, bp.groups[k].variant, grids[k], st);
+      if (e == hipSuccess) e = launch_group(bp, b, k, grids[k], st);
     }
     return e;
   }
@@ -570,7 +588,7 @@ hipError_t enqueue_groups(const BatchPlan &bp, uint8_t *ws, const std::vector<in
     b.arena += first * bp.arena_bytes;            // disjoint arena slices per group
     first += (uint64_t)grids[k];
     if (e == hipSuccess) e = lsaw::launch_batch_reset(b.counter, gs);
-    if (e == hipSuccess) e = lsaw::launch_batch(b, bp.groups[k].variant, grids[k], gs);
+    if (e == hipSuccess) e = launch_group(bp, b, k, grids[k], gs);
     if (e == hipSuccess && k > 0) e = hipEventRecord(ss->join[k], gs);
   }
   for (size_t k = 1; k < bp.groups.size() && e == hipSuccess; ++k) e = hipStreamWaitEvent(st, ss->join[k], 0);
@@ -648,10 +666,14 @@ struct labs_batch_graph {
 
 extern "C" {
 
-int32_t labs_batch_workspace_bytes(const labs_instance *inst, int32_t n_inst, uint64_t *bytes) {
+}  // extern "C"
+
+namespace {
+
+int32_t batch_workspace_bytes(const labs_instance *inst, int32_t n_inst, uint64_t *bytes, bool full) {
   if (!bytes) return fail(LABS_EINVAL, "NULL bytes");
   BatchPlan bp;
-  int32_t rc = plan_batch(inst, n_inst, bp);
+  int32_t rc = plan_batch(inst, n_inst, bp, full);
   if (rc != LABS_OK) return rc;
   // Groups one after another: the largest group's grid of arena slices.
   // (A workspace with a slice for every workgroup of every group lets the
@@ -659,7 +681,7 @@ int32_t labs_batch_workspace_bytes(const labs_instance *inst, int32_t n_inst, ui
   int64_t g = 1;
   for (const BatchGroup &grp : bp.groups) {
     int64_t resident = 0;
-    rc = device_resident_blocks(grp.variant, &resident);
+    rc = device_resident_blocks(grp.variant, bp.full, &resident);
     if (rc != LABS_OK) return rc;
     g = std::max<int64_t>(g, std::min<int64_t>(grp.count, resident));
   }
@@ -667,10 +689,10 @@ int32_t labs_batch_workspace_bytes(const labs_instance *inst, int32_t n_inst, ui
   return ok();
 }
 
-int32_t labs_walks_batch(const labs_instance *inst, int32_t n_inst, void *workspace,
-                         uint64_t ws_bytes, void *stream) {
+int32_t walks_batch(const labs_instance *inst, int32_t n_inst, void *workspace, uint64_t ws_bytes,
+                    void *stream, bool full) {
   BatchPlan bp;
-  int32_t rc = plan_batch(inst, n_inst, bp);
+  int32_t rc = plan_batch(inst, n_inst, bp, full);
   if (rc != LABS_OK) return rc;
   if (bp.items.empty()) return ok();
   if (!workspace) return fail(LABS_EINVAL, "NULL workspace");
@@ -688,6 +710,28 @@ int32_t labs_walks_batch(const labs_instance *inst, int32_t n_inst, void *worksp
   if (e == hipSuccess) e = enqueue_groups(bp, ws, grids, concurrent, st);
   if (e != hipSuccess) return fail(LABS_EDEVICE, "batch launch: %s", hipGetErrorString(e));
   return ok();
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t labs_batch_workspace_bytes(const labs_instance *inst, int32_t n_inst, uint64_t *bytes) {
+  return batch_workspace_bytes(inst, n_inst, bytes, false);
+}
+
+int32_t labs_walks_batch(const labs_instance *inst, int32_t n_inst, void *workspace,
+                         uint64_t ws_bytes, void *stream) {
+  return walks_batch(inst, n_inst, workspace, ws_bytes, stream, false);
+}
+
+int32_t labs_full_batch_workspace_bytes(const labs_instance *inst, int32_t n_inst, uint64_t *bytes) {
+  return batch_workspace_bytes(inst, n_inst, bytes, true);
+}
+
+int32_t labs_full_walks_batch(const labs_instance *inst, int32_t n_inst, void *workspace,
+                              uint64_t ws_bytes, void *stream) {
+  return walks_batch(inst, n_inst, workspace, ws_bytes, stream, true);
 }
 
 int32_t labs_batch_graph_create(const labs_instance *inst, int32_t n_inst, void *workspace,

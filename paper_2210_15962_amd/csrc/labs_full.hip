@@ -279,11 +279,24 @@ __host__ __device__ constexpr CodeSet words_mask(int nw, int G) {
   return m;
 }
 
+// Codes of every class in [nlo, nhi] (a batch kernel runs the lengths of
+// several classes on the largest one's geometry).
+__host__ __device__ constexpr CodeSet words_mask_range(int nlo, int nhi, int G) {
+  CodeSet m{{0, 0, 0}};
+  for (int c = nlo; c <= nhi; ++c) {
+    const CodeSet x = words_mask(c, G);
+    for (int i = 0; i < 3; ++i) m.w[i] |= x.w[i];
+  }
+  return m;
+}
+template <int NLO, int NHI>
+struct ClassCodes { static constexpr CodeSet value = words_mask_range(NLO, NHI, kG); };
+
 // Calls f(FW, BW) as compile-time constants for a wave-uniform code; a code
-// outside the class's set takes the all-words form, valid for every candidate.
-template <int NW, class F>
+// outside the kernel's set takes the all-words form, valid for every candidate.
+template <int NW, class Codes, class F>
 __device__ __forceinline__ void with_words(int code, F &&f) {
-  constexpr CodeSet kMask = words_mask(NW, kG);
+  constexpr CodeSet kMask = Codes::value;
   constexpr int kFull = NW * 16 + NW;
   const int eff = code_in(kMask, code) ? code : kFull;
   static_for<0, 16 * NW + NW + 1>([&](auto cc) {
@@ -340,13 +353,36 @@ __device__ __forceinline__ void apply_move_planes(const uint32_t *row, const uin
 template <int NW>
 struct FullOccupancy { static constexpr int value = NW <= 4 ? 4 : (NW <= 7 ? 3 : 2); };
 
-template <int NW>
-__global__ void __launch_bounds__(kBlock, FullOccupancy<NW>::value) full_walk_kernel(const WalkLaunch a) {
+// One workgroup's share: up to kBlock / kG walks of one length L.
+struct FullTask {
+  const uint64_t *starts;   // first pivots of the instance ([walk][KW]) or nullptr
+  uint64_t seed;            // seeded starts: SplitMix64 of (seed, walk index)
+  int32_t L;
+  int32_t n_block;          // walks of this block
+  int64_t walk_begin;       // instance index of the block's first walk
+  int64_t walk_len;
+  uint64_t *best_seq;
+  int32_t *best_E;
+  int64_t *steps_done;
+  uint64_t *digest;
+  int16_t *trace_j;
+  int32_t *trace_E;
+  int64_t n_trace;
+  uint32_t *cap_steps;
+  uint8_t *tables;          // table of block slot s at tables + s * table_bytes
+  uint64_t table_bytes;
+  uint32_t n_buckets;
+};
+
+// The walks of one block (geometry of class NW, which serves every shorter
+// length too; kFLO the narrowest entry format of the lengths the kernel
+// runs; Codes its run codes).
+template <int NW, int kFLO, class Codes>
+__device__ __forceinline__ void run_full_block(const FullTask &a, uint8_t *lds) {
   using Gm = Geom<NW>;
   constexpr int G = kG, K = kK, lgG = 2;
   static_assert(G == 4, "lane index arithmetic assumes four lanes per walk");
   static_assert(Gm::NLOC <= 64, "one exclusion word per lane");
-  extern __shared__ __align__(16) uint8_t lds[];
   uint32_t *desc = reinterpret_cast<uint32_t *>(lds);
   uint8_t *cols = lds + Gm::cols_off();
   uint32_t *runs = reinterpret_cast<uint32_t *>(lds + Gm::runs_off());
@@ -354,9 +390,8 @@ __global__ void __launch_bounds__(kBlock, FullOccupancy<NW>::value) full_walk_ke
 
   const int L = a.L;
   const int KW = (L + 63) / 64;
-  const int64_t first = (int64_t)blockIdx.x * (kBlock / G);
-  const int n_block = (int)min((int64_t)(kBlock / G), a.n_walks - first);
-  uint8_t *tables = a.tables + (uint64_t)first * a.table_bytes;
+  const int n_block = a.n_block;
+  uint8_t *tables = a.tables;
 
   build_descriptors<NW>(desc, L);
   const int nmax = (L + G - 1) / G;              // candidate-loop iterations
@@ -392,12 +427,11 @@ __global__ void __launch_bounds__(kBlock, FullOccupancy<NW>::value) full_walk_ke
   const int tid = (int)threadIdx.x;
   const int r = tid % G;                        // lane rank inside the walk group
   const int slot = tid / G;                     // walk slot inside the block
-  const int64_t walk = a.walk_begin + first + slot;
+  const int64_t walk = a.walk_begin + slot;
   bool active = slot < n_block;
   const uint32_t colbase = (uint32_t)tid * 4u;
   uint32_t *colw = reinterpret_cast<uint32_t *>(cols);
-  // visited-table entry format of this length (the formats of the class)
-  constexpr int kFLO = entry_format(32 * (NW - 1) + 2);
+  // visited-table entry format of this length (within the kernel's formats)
   constexpr int kFHI = entry_format(Gm::LMAX);
   const int efmt = entry_format(L);
   const uint32_t ev = even_c_mask(L);
@@ -553,7 +587,7 @@ __global__ void __launch_bounds__(kBlock, FullOccupancy<NW>::value) full_walk_ke
       const uint32_t e0 = __builtin_amdgcn_readfirstlane(runs[sr]);
       const int ib = (int)(e0 >> 8);
       const int ie = (int)(__builtin_amdgcn_readfirstlane(runs[sr + 1]) >> 8);
-      with_words<NW>((int)(e0 & 0xFFu), [&](auto Fc, auto Bc) __attribute__((always_inline)) {
+      with_words<NW, Codes>((int)(e0 & 0xFFu), [&](auto Fc, auto Bc) __attribute__((always_inline)) {
         constexpr int F = decltype(Fc)::value, B = decltype(Bc)::value;
         auto scan = [&](auto BPc) __attribute__((always_inline)) {
           constexpr int BPv = decltype(BPc)::value;
@@ -599,7 +633,7 @@ __global__ void __launch_bounds__(kBlock, FullOccupancy<NW>::value) full_walk_ke
           const uint32_t e0 = __builtin_amdgcn_readfirstlane(runs[sr]);
           const int ib = (int)(e0 >> 8);
           const int ie = (int)(__builtin_amdgcn_readfirstlane(runs[sr + 1]) >> 8);
-          with_words<NW>((int)(e0 & 0xFFu), [&](auto Fc, auto Bc) __attribute__((always_inline)) {
+          with_words<NW, Codes>((int)(e0 & 0xFFu), [&](auto Fc, auto Bc) __attribute__((always_inline)) {
             constexpr int F = decltype(Fc)::value, B = decltype(Bc)::value;
             uint64_t xw = ex >> ib;
 #pragma unroll 1
@@ -755,6 +789,99 @@ __global__ void __launch_bounds__(kBlock, FullOccupancy<NW>::value) full_walk_ke
 }
 
 template <int NW>
+__global__ void __launch_bounds__(kBlock, FullOccupancy<NW>::value) full_walk_kernel(const WalkLaunch w) {
+  extern __shared__ __align__(16) uint8_t lds[];
+  const int64_t first = (int64_t)blockIdx.x * (kBlock / kG);
+  FullTask t;
+  t.starts = w.starts;
+  t.seed = w.seed;
+  t.L = w.L;
+  t.n_block = (int32_t)min((int64_t)(kBlock / kG), w.n_walks - first);
+  t.walk_begin = w.walk_begin + first;
+  t.walk_len = w.walk_len;
+  t.best_seq = w.best_seq;
+  t.best_E = w.best_E;
+  t.steps_done = w.steps_done;
+  t.digest = w.digest;
+  t.trace_j = w.trace_j;
+  t.trace_E = w.trace_E;
+  t.n_trace = w.n_trace;
+  t.cap_steps = w.cap_steps;
+  t.tables = w.tables + (uint64_t)first * w.table_bytes;
+  t.table_bytes = w.table_bytes;
+  t.n_buckets = w.n_buckets;
+  run_full_block<NW, entry_format(32 * (NW - 1) + 2), ClassCodes<NW, NW>>(t, lds);
+}
+
+// Persistent whole-space batch kernel: every workgroup takes (instance, block)
+// items from a device counter until the queue is empty.  Built for the
+// largest class NHI of a group of classes [NLO, NHI] of equal occupancy;
+// shorter lengths skip the unused lag words.
+// Waves per SIMD of the batch kernels: one fewer than the walk kernels of
+// their largest class (the union of several classes' run codes needs more
+// registers; at the walk kernels' occupancy it spills).
+template <int NHI>
+struct FullBatchOccupancy { static constexpr int value = NHI <= 4 ? 3 : 2; };
+
+template <int NLO, int NHI>
+__global__ void __launch_bounds__(kBlock, FullBatchOccupancy<NHI>::value) full_batch_kernel(const BatchLaunch b) {
+  extern __shared__ __align__(16) uint8_t lds[];
+  __shared__ int64_t s_item;
+  uint8_t *arena = b.arena + (uint64_t)blockIdx.x * b.arena_bytes;
+  for (;;) {
+    __syncthreads();                       // previous item finished, s_item consumed
+    if (threadIdx.x == 0) s_item = (int64_t)atomicAdd(b.counter, 1u);
+    __syncthreads();
+    const int64_t it = s_item;
+    if (it >= b.n_items) break;            // uniform: every wave leaves together
+    const BatchItemDev item = b.items[it];
+    const BatchInstanceDev &in = b.inst[item.inst];
+    FullTask t;
+    t.starts = in.starts;
+    t.seed = in.seed;
+    t.L = in.L;
+    t.n_block = item.n_walks;
+    t.walk_begin = item.walk_begin;
+    t.walk_len = in.walk_len;
+    t.best_seq = in.best_seq;
+    t.best_E = in.best_E;
+    t.steps_done = in.steps_done;
+    t.digest = in.digest;
+    t.trace_j = in.trace_j;
+    t.trace_E = in.trace_E;
+    t.n_trace = in.n_trace;
+    t.cap_steps = in.cap_steps;
+    t.tables = in.tables ? in.tables + (uint64_t)item.walk_begin * in.table_bytes : arena;
+    t.table_bytes = in.table_bytes;
+    t.n_buckets = in.n_buckets;
+    run_full_block<NHI, entry_format(NLO == 1 ? 3 : 32 * (NLO - 1) + 2), ClassCodes<NLO, NHI>>(t, lds);
+  }
+}
+
+// Class groups of the batch kernels: classes of equal occupancy share the
+// largest one's kernel.
+__host__ __device__ constexpr int batch_group_of(int nw) { return nw <= 4 ? 4 : (nw <= 7 ? 7 : 8); }
+
+template <int NLO, int NHI>
+static hipError_t launch_batch_g(const BatchLaunch &b, int grid, hipStream_t stream) {
+  const size_t lds = Geom<NHI>::lds_bytes();
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(full_batch_kernel<NLO, NHI>),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((full_batch_kernel<NLO, NHI>), dim3((unsigned)grid), dim3(kBlock), lds, stream, b);
+  return hipGetLastError();
+}
+
+template <int NLO, int NHI>
+static hipError_t blocks_per_cu_g(int *blocks) {
+  const void *fn = reinterpret_cast<const void *>(full_batch_kernel<NLO, NHI>);
+  const size_t lds = Geom<NHI>::lds_bytes();
+  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, fn, kBlock, lds);
+}
+
+template <int NW>
 static hipError_t launch_nw(const WalkLaunch &w, hipStream_t stream) {
   const size_t lds = Geom<NW>::lds_bytes();
   auto kern = full_walk_kernel<NW>;
@@ -771,6 +898,25 @@ static hipError_t launch_nw(const WalkLaunch &w, hipStream_t stream) {
 }  // namespace full
 
 int full_lanes_per_walk() { return full::kG; }
+
+int full_batch_variant(int nw) { return full::batch_group_of(nw); }
+
+hipError_t full_batch_blocks_per_cu(int variant, int *blocks) {
+  switch (variant) {
+    case 4: return full::blocks_per_cu_g<1, 4>(blocks);
+    case 7: return full::blocks_per_cu_g<5, 7>(blocks);
+    default: return full::blocks_per_cu_g<8, 8>(blocks);
+  }
+}
+
+hipError_t launch_full_batch(const BatchLaunch &b, int variant, int grid, hipStream_t stream) {
+  if (grid <= 0) return hipSuccess;
+  switch (variant) {
+    case 4: return full::launch_batch_g<1, 4>(b, grid, stream);
+    case 7: return full::launch_batch_g<5, 7>(b, grid, stream);
+    default: return full::launch_batch_g<8, 8>(b, grid, stream);
+  }
+}
 
 size_t full_walk_lds_bytes(int32_t L) {
   switch (full_lag_words_for(L)) {

@@ -136,6 +136,11 @@ size_t walk_lds_bytes(int32_t L);
 int full_lanes_per_walk();
 size_t full_walk_lds_bytes(int32_t L);
 hipError_t launch_full_walks(const WalkLaunch &w, hipStream_t stream);
+// Whole-space batches: kernel group of lag-word class nw (4: classes 1-4,
+// 7: classes 5-7, 8: class 8), resident workgroups per CU, and the launch.
+int full_batch_variant(int nw);
+hipError_t full_batch_blocks_per_cu(int variant, int *blocks);
+hipError_t launch_full_batch(const BatchLaunch &b, int variant, int grid, hipStream_t stream);
 // Batch kernel of lag-word class nw (2..6; class 1 runs on the class-2 kernel).
 int batch_variant(int nw);
 size_t batch_lds_bytes(int variant);

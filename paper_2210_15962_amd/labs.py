@@ -131,6 +131,10 @@ def lib():
         L.labs_batch_workspace_bytes.restype = I32
         L.labs_walks_batch.argtypes = [ctypes.POINTER(Instance), I32, VP, U64, VP]
         L.labs_walks_batch.restype = I32
+        L.labs_full_batch_workspace_bytes.argtypes = [ctypes.POINTER(Instance), I32, ctypes.POINTER(U64)]
+        L.labs_full_batch_workspace_bytes.restype = I32
+        L.labs_full_walks_batch.argtypes = [ctypes.POINTER(Instance), I32, VP, U64, VP]
+        L.labs_full_walks_batch.restype = I32
         L.labs_batch_graph_create.argtypes = [ctypes.POINTER(Instance), I32, VP, U64,
                                               ctypes.POINTER(VP)]
         L.labs_batch_graph_create.restype = I32
@@ -410,9 +414,9 @@ def full_walks(L: int, n_walks: int, walk_len: int, seed: int = 0, starts_t=None
 
 
 # ----------------------------------------------------------- mixed-L batches
-def _alloc_outputs(L, n_walks, walk_len, n_trace, device="cuda", cap_steps=False):
+def _alloc_outputs(L, n_walks, walk_len, n_trace, device="cuda", cap_steps=False, full=False):
     import torch
-    W = key_words(L)
+    W = full_key_words(L) if full else key_words(L)
     res = {
         "best_seq": torch.empty((n_walks, W), dtype=torch.int64, device=device),
         "best_E": torch.empty(n_walks, dtype=torch.int32, device=device),
@@ -463,6 +467,33 @@ def walks_batch(specs, workspace=None, stream=None, device="cuda"):
         workspace = alloc_workspace(b.value, device=device)
     _check(lib().labs_walks_batch(arr, len(specs), _dptr(workspace), workspace.numel(),
                                   _stream_handle(stream)))
+    _in_use_on(stream, workspace, *[t for r in results for t in r.values()],
+               *[sp.get("starts_t") for sp in specs])
+    return results
+
+
+def full_batch_workspace_bytes(specs) -> int:
+    results = [_alloc_outputs(sp["L"], 0, 0, 0, full=True) for sp in specs]
+    arr = make_instances(specs, results)
+    b = U64(0)
+    _check(lib().labs_full_batch_workspace_bytes(arr, len(specs), ctypes.byref(b)))
+    return int(b.value)
+
+
+def full_walks_batch(specs, workspace=None, stream=None, device="cuda"):
+    """Whole-space instances (list of dicts as for walks_batch, L in [3, 255])
+    in persistent launches (labs_full_walks_batch).  Returns one result dict
+    per instance, like full_walks()."""
+    results = [_alloc_outputs(sp["L"], sp["n_walks"], sp["walk_len"], sp.get("n_trace", 0), device,
+                              sp.get("cap_steps", False), full=True)
+               for sp in specs]
+    arr = make_instances(specs, results)
+    if workspace is None:
+        b = U64(0)
+        _check(lib().labs_full_batch_workspace_bytes(arr, len(specs), ctypes.byref(b)))
+        workspace = alloc_workspace(b.value, device=device)
+    _check(lib().labs_full_walks_batch(arr, len(specs), _dptr(workspace), workspace.numel(),
+                                       _stream_handle(stream)))
     _in_use_on(stream, workspace, *[t for r in results for t in r.values()],
                *[sp.get("starts_t") for sp in specs])
     return results

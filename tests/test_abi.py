@@ -152,6 +152,24 @@ def test_batch_validation_before_any_launch():
     assert lib.labs_walks_batch(arr, 0, ws, 0, None) == labs.LABS_OK            # nothing to run
 
 
+def test_full_batch_validation_before_any_launch():
+    lib = labs.lib()
+    empty = {"best_seq": None, "best_E": None, "steps_done": None, "digest": None}
+    ws = ctypes.c_void_p(1)
+    b = labs.U64(0)
+    for bad in (dict(L=256, n_walks=4, walk_len=10), dict(L=2, n_walks=4, walk_len=10),
+                dict(L=64, n_walks=4, walk_len=10, lanes_per_walk=2),   # whole space: 4 lanes
+                dict(L=64, n_walks=4, walk_len=-1), dict(L=64, n_walks=4, walk_len=10)):  # no outputs
+        arr = labs.make_instances([bad], [empty])
+        assert lib.labs_full_walks_batch(arr, 1, ws, 1 << 30, None) == labs.LABS_EINVAL
+        assert lib.labs_full_batch_workspace_bytes(arr, 1, ctypes.byref(b)) in (
+            labs.LABS_EINVAL, labs.LABS_EDEVICE)           # outputs are checked before the device
+    arr = labs.make_instances([dict(L=256, n_walks=4, walk_len=10)], [empty])
+    assert lib.labs_full_batch_workspace_bytes(arr, 1, ctypes.byref(b)) == labs.LABS_EINVAL
+    assert lib.labs_full_walks_batch(arr, -1, ws, 1 << 30, None) == labs.LABS_EINVAL
+    assert lib.labs_full_walks_batch(arr, 0, ws, 0, None) == labs.LABS_OK       # nothing to run
+
+
 def test_serve_validation_before_any_device_call():
     lib = labs.lib()
     h = ctypes.c_void_p()

@@ -145,3 +145,52 @@ def test_bench_workload_65536_walks(L, steps, prefix):
     short = labs.full_walks(L, len(idx), prefix, starts_t=st, plan=plan)
     torch.cuda.synchronize()
     _compare(L, keys[idx], short, prefix)
+
+
+def _first(res, k):
+    return {key: (v[:k] if v is not None else None) for key, v in res.items()}
+
+
+def test_batch_of_mixed_lengths_matches_standalone_and_oracle():
+    """labs_full_walks_batch: instances across the three kernel groups
+    (classes 1-4, 5-7, 8), ragged walk counts, an empty walk, explicit starts
+    and traces; every instance equals its standalone labs_full_walks run bit
+    for bit, and the oracle on its first walks."""
+    labs = _labs()
+    Ls = [3, 16, 33, 64, 97, 128, 129, 130, 161, 200, 225, 226, 255]
+    specs = []
+    for i, L in enumerate(Ls):
+        n = [70, 64, 1, 130][i % 4]
+        wl = 300 if L <= 64 else (120 if L <= 128 else 40)
+        specs.append(dict(L=L, n_walks=n, walk_len=wl, seed=100 + i, n_trace=min(n, 2)))
+    specs.append(dict(L=50, n_walks=5, walk_len=0, seed=7))
+    keys140 = I.random_full_keys(140, 20, seed=5)
+    specs.append(dict(L=140, n_walks=20, walk_len=60,
+                      starts_t=torch.from_numpy(I.as_int64_keys(keys140)).cuda()))
+    print(f"[full batch] {len(specs)} instances", flush=True)
+    res = labs.full_walks_batch(specs)
+    torch.cuda.synchronize()
+    for sp, r in zip(specs, res):
+        alone = labs.full_walks(sp["L"], sp["n_walks"], sp["walk_len"], seed=sp.get("seed", 0),
+                                starts_t=sp.get("starts_t"), n_trace=sp.get("n_trace", 0))
+        torch.cuda.synchronize()
+        for key in ("best_seq", "best_E", "steps_done", "digest", "trace_j", "trace_E"):
+            if key in alone and alone[key] is not None:
+                np.testing.assert_array_equal(r[key].cpu().numpy(), alone[key].cpu().numpy())
+    for idx in (0, 3, 6, 9, 12):
+        sp = specs[idx]
+        k = min(sp["n_walks"], 2)
+        _compare(sp["L"], O.full_starts(sp["L"], k, sp["seed"]), _first(res[idx], k), sp["walk_len"],
+                 n_trace=min(k, sp["n_trace"]))
+    _compare(140, keys140[:3], _first(res[-1], 3), 60)
+    assert (res[-2]["steps_done"].cpu().numpy() == 0).all()
+
+
+def test_batch_rejects_invalid_instances():
+    labs = _labs()
+    for bad in (dict(L=256, n_walks=4, walk_len=10), dict(L=2, n_walks=4, walk_len=10),
+                dict(L=64, n_walks=4, walk_len=10, lanes_per_walk=2),
+                dict(L=64, n_walks=4, walk_len=-1)):
+        with pytest.raises(labs.LabsError) as e:
+            labs.full_walks_batch([dict(L=20, n_walks=8, walk_len=5), bad])
+        assert e.value.code == labs.LABS_EINVAL
