@@ -366,6 +366,7 @@ def run_mixed_batch(steps: int, warmup: int, autotune: bool):
         caps_all = [caps_all[k] + int(c[k]) for k in range(4)]
     g.close()
     achieved = alg / (ms / steps / 1e3)
+    tag = f"batch_kernel@{kernel_source_tag()}"
     lanes = {}
     for L in Ls:
         k = labs.tune_get(L)[0]
@@ -376,8 +377,8 @@ def run_mixed_batch(steps: int, warmup: int, autotune: bool):
             "ms_per_launch": ms / steps, "replays": steps,
             "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": INT32_VALU_PEAK / 1e12,
                          "unit": "TOP/s", "frac": achieved / INT32_VALU_PEAK,
-                         "kernel": f"batch_kernel@{kernel_source_tag()}",
-                         "alg_ops_per_launch": alg,
+                         "traffic": load_counter_traffic(tag, "batch_kernel_mixedL_61_223_traffic.json"),
+                         "kernel": tag, "alg_ops_per_launch": alg,
                          "scans_by_plane_cap": {str(c or "all"): v for c, v in zip(CAPS, caps_all)}},
             "autotuned": autotune, "tune_seconds": t_tune,
             "instances_by_lanes_per_walk": {str(k): v for k, v in sorted(lanes.items())},
