@@ -329,7 +329,8 @@ int32_t labs_autotune(int32_t L, int64_t n_walks, int64_t walk_len, void *worksp
  * chunk_steps moves.  Walk state and visited tables stay in device memory
  * between launches; a finished request is delivered and its memory reused at
  * once.  Each request's results equal a standalone labs_walks run with the
- * same (L, n_walks, walk_len, seed / starts).
+ * same (L, n_walks, walk_len, seed / starts) -- or, on a whole-space server
+ * (labs_serve_cfg.whole_space = 1), a standalone labs_full_walks run.
  */
 typedef struct labs_server labs_server;
 
@@ -341,6 +342,9 @@ typedef struct labs_serve_cfg {
   int64_t chunk_steps;     /* moves per launch per request; 0 = no limit (launches
                               end when a request can be admitted or has finished) */
   double load_factor;      /* visited-table load factor; 0 = default 0.5 */
+  int32_t whole_space;     /* 1: the server takes whole-space requests (L in [3, 255],
+                              any parity; keys as for labs_full_walks, four lanes per
+                              walk); 0: skew-symmetric requests */
 } labs_serve_cfg;
 
 typedef struct labs_serve_result {
@@ -369,7 +373,8 @@ int32_t labs_serve_destroy(labs_server *server);
 
 /*
  * submit: queue one request (non-blocking).  starts is a host array
- * [n_walks][W] that is copied, or NULL for seeded starts.  Returns LABS_EBUSY
+ * [n_walks][W] that is copied, or NULL for seeded starts (W and the key
+ * layout of labs_walks, or of labs_full_walks on a whole-space server).  Returns LABS_EBUSY
  * when the host queue is full, LABS_EINVAL for invalid arguments or a request
  * whose footprint exceeds the whole pool.
  */

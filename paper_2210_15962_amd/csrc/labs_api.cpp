@@ -900,10 +900,10 @@ int32_t set_error(int32_t code, const char *fmt, ...) {
 int32_t clear_error() { return ok(); }
 
 bool table_geometry(int32_t L, int64_t walk_len, double load_factor, uint32_t *n_buckets,
-                    uint64_t *table_bytes) {
-  labs_plan lp{2, load_factor, 0};
+                    uint64_t *table_bytes, bool full) {
+  labs_plan lp{full ? 0 : 2, load_factor, 0};
   Plan p;
-  if (make_plan(L, walk_len, &lp, p) != LABS_OK) return false;
+  if ((full ? make_full_plan(L, walk_len, &lp, p) : make_plan(L, walk_len, &lp, p)) != LABS_OK) return false;
   *n_buckets = p.n_buckets;
   *table_bytes = p.table_bytes;
   return true;

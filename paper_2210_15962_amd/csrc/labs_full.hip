@@ -372,12 +372,27 @@ struct FullTask {
   uint8_t *tables;          // table of block slot s at tables + s * table_bytes
   uint64_t table_bytes;
   uint32_t n_buckets;
+  // serving form only (see the skew-symmetric batch kernel's)
+  WalkState *state;         // per-walk progress across launches
+  uint8_t *wstat;           // per-walk status: 0 not started, 1 resume, 2 finished
+  int64_t step_end;         // a walk stops when it has made this many moves
+  const uint32_t *preempt;  // host stop flag polled every 64 moves, or nullptr
+  uint32_t *done_flag;      // set to 1 if the block ends with every walk finished
 };
+
+// A nonzero stop word from the host (fine-grained memory: read past the
+// caches), read by one lane of the wave.
+__device__ __forceinline__ bool full_stop_requested(const uint32_t *flag) {
+  uint32_t v = 0u;
+  if (__lane_id() == 0) v = __hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+  return __builtin_amdgcn_readfirstlane(v) != 0u;
+}
 
 // The walks of one block (geometry of class NW, which serves every shorter
 // length too; kFLO the narrowest entry format of the lengths the kernel
-// runs; Codes its run codes).
-template <int NW, int kFLO, class Codes>
+// runs; Codes its run codes; kSv the serving form: walks that pause and
+// resume across launches).
+template <int NW, int kFLO, class Codes, bool kSv = false>
 __device__ __forceinline__ void run_full_block(const FullTask &a, uint8_t *lds) {
   using Gm = Geom<NW>;
   constexpr int G = kG, K = kK, lgG = 2;
@@ -414,11 +429,21 @@ __device__ __forceinline__ void run_full_block(const FullTask &a, uint8_t *lds) 
     runs[kRunSlots - 1] = (uint32_t)n;
   }
   for (int x = (int)threadIdx.x; x < L; x += blockDim.x) zob[x] = zobrist_word(x);
-  {
+  const uint4 z = {0u, 0u, 0u, 0u};
+  if (kSv && a.wstat) {
+    // Walks resumed from an earlier launch keep their tables: clear only the
+    // tables of walks that start now.
+    const uint64_t n16 = a.table_bytes / 16u;
+    for (int sl = 0; sl < n_block; ++sl) {
+      if (a.wstat[a.walk_begin + sl] != 0u) continue;      // uniform
+      uint4 *p = reinterpret_cast<uint4 *>(tables + (uint64_t)sl * a.table_bytes);
+#pragma unroll 4
+      for (uint64_t q = threadIdx.x; q < n16; q += kBlock) p[q] = z;
+    }
+  } else {
     // Clear the visited tables of this block's walks (contiguous, coalesced).
     uint4 *p = reinterpret_cast<uint4 *>(tables);
     const uint64_t n16 = (uint64_t)max(n_block, 0) * (a.table_bytes / 16u);
-    const uint4 z = {0u, 0u, 0u, 0u};
 #pragma unroll 4
     for (uint64_t q = threadIdx.x; q < n16; q += kBlock) p[q] = z;
   }
@@ -429,6 +454,11 @@ __device__ __forceinline__ void run_full_block(const FullTask &a, uint8_t *lds) 
   const int slot = tid / G;                     // walk slot inside the block
   const int64_t walk = a.walk_begin + slot;
   bool active = slot < n_block;
+  // Status of the walk from earlier launches (serving form).
+  const uint32_t wst = (kSv && a.wstat && active) ? (uint32_t)a.wstat[walk] : 0u;
+  const bool fresh = wst == 0u;                 // starts at P_1 in this launch
+  const bool skip = wst == 2u;                  // finished earlier: nothing to do
+  if (skip) active = false;
   const uint32_t colbase = (uint32_t)tid * 4u;
   uint32_t *colw = reinterpret_cast<uint32_t *>(cols);
   // visited-table entry format of this length (within the kernel's formats)
@@ -437,9 +467,16 @@ __device__ __forceinline__ void run_full_block(const FullTask &a, uint8_t *lds) 
   const uint32_t ev = even_c_mask(L);
   constexpr int KWM = (Gm::LMAX + 63) / 64;        // key words any length of the class needs
 
-  // ---- first pivot -----------------------------------------------------------
+  // ---- first pivot, or the pivot reached by an earlier launch -----------------
   Key P{0, 0, 0};
-  if (active) {
+  WalkState ws{};
+  if (active && !fresh) {
+    ws = a.state[walk];
+    P.w0 = ws.P[0];
+    P.w1 = ws.P[1];
+    P.w2 = ws.P[2];
+    P.w3 = ws.P[3];
+  } else if (active) {
     auto start_word = [&](int t) -> uint64_t {
       if (t >= KW) return 0ull;
       uint64_t v;
@@ -512,14 +549,24 @@ __device__ __forceinline__ void run_full_block(const FullTask &a, uint8_t *lds) 
   uint64_t h = 0;
   int64_t steps = 0;
   uint32_t prev_im1 = 0xFFFFFFFFu;
+  bool trapped = false;
   uint8_t *table = tables + (uint64_t)(active ? slot : 0) * a.table_bytes;
+  if (active && !fresh) {
+    bestE = ws.bestE;
+    bestP = Key{ws.bestP[0], ws.bestP[1], ws.bestP[2], ws.bestP[3]};
+    h = ws.h;
+    steps = ws.steps;
+    prev_im1 = ws.prev_jm1;
+    trapped = ws.trapped != 0u;
+    if (trapped) active = false;
+  }
 
   uint32_t hP = 0u;
 #pragma unroll 1
   for (int x = 0; x < L; ++x) hP ^= key_bit(P, x) ? zob[x] : 0u;
 
   // Insert P_1 (the table is empty: first entry of its home bucket).
-  if (active && r == 0)
+  if (active && fresh && r == 0)
     store_entry<kFLO, kFHI>(table + (uint64_t)bucket_of_hash(hP, a.n_buckets) * kBucketBytes, 0u, P, efmt);
 
   // Local candidates of lane r: i = r + 1 + G*it; their signs in registers
@@ -553,8 +600,26 @@ __device__ __forceinline__ void run_full_block(const FullTask &a, uint8_t *lds) 
   uint32_t ncap4 = 0u, ncap5 = 0u, ncap6 = 0u, ncap0 = 0u;
   const bool tracing = active && walk < a.n_trace;
 
-  for (int64_t step = 0; step < a.walk_len; ++step) {
+  // Serving form: a wave makes as many moves as its nearest-to-done walk has
+  // left (walks that ran in different waves before may stand at different
+  // move counts); walks still short of the end continue in the next launch.
+  const int64_t step_stop = kSv ? min(a.step_end, a.walk_len) : a.walk_len;
+  int64_t lim = step_stop;
+  if constexpr (kSv) {
+    if (steps >= step_stop) active = false;
+    int64_t rem = active ? step_stop - steps : INT64_MAX;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      const int64_t o = __shfl_xor(rem, off);
+      rem = o < rem ? o : rem;
+    }
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)(uint64_t)rem);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)rem >> 32));
+    lim = (int64_t)(((uint64_t)hi << 32) | lo);
+  }
+  for (int64_t step = 0; step < lim; ++step) {
     if (__ballot(active) == 0ull) break;
+    if (kSv && a.preempt && (step & 63) == 63 && full_stop_requested(a.preempt)) break;
     // Excluded local candidates (bit it <-> i = r + 1 + G*it): the
     // predecessor, then every candidate found visited during this step.
     uint64_t ex = 0ull;
@@ -735,6 +800,7 @@ __device__ __forceinline__ void run_full_block(const FullTask &a, uint8_t *lds) 
     if (active) {
       if (win == kKeyMax) {
         active = false;         // trapped walk stops here
+        trapped = true;
       } else {
         const uint32_t im1 = win & 0xFFu;
         const int32_t dE = 4 * ((int32_t)(win >> 8) - kBias);
@@ -763,8 +829,8 @@ __device__ __forceinline__ void run_full_block(const FullTask &a, uint8_t *lds) 
         if (E < bestE) { bestE = E; bestP = P; }
         h = mix64(h ^ (((uint64_t)(im1 + 1u) << 32) | (uint64_t)(uint32_t)E));
         if (tracing && r == 0) {
-          a.trace_j[walk * a.walk_len + step] = (int16_t)(im1 + 1u);
-          a.trace_E[walk * a.walk_len + step] = E;
+          a.trace_j[walk * a.walk_len + steps] = (int16_t)(im1 + 1u);
+          a.trace_E[walk * a.walk_len + steps] = E;
         }
         prev_im1 = im1;
         ++steps;
@@ -772,12 +838,25 @@ __device__ __forceinline__ void run_full_block(const FullTask &a, uint8_t *lds) 
     }
   }
 
-  if (a.cap_steps && slot < n_block && r == 0) {
+  const bool finished = trapped || steps >= a.walk_len;
+  if (kSv && a.state && slot < n_block && r == 0 && !skip) {
+    WalkState o{};
+    o.P[0] = P.w0; o.P[1] = P.w1; o.P[2] = P.w2; o.P[3] = P.w3;
+    o.bestP[0] = bestP.w0; o.bestP[1] = bestP.w1; o.bestP[2] = bestP.w2; o.bestP[3] = bestP.w3;
+    o.h = h;
+    o.steps = steps;
+    o.bestE = bestE;
+    o.prev_jm1 = prev_im1;
+    o.trapped = trapped ? 1u : 0u;
+    a.state[walk] = o;
+  }
+  if (kSv && a.wstat && slot < n_block && r == 0 && !skip) a.wstat[walk] = finished ? 2u : 1u;
+  if (a.cap_steps && slot < n_block && r == 0 && !skip) {
     uint4 v;
     v.x = ncap4; v.y = ncap5; v.z = ncap6; v.w = ncap0;
     *reinterpret_cast<uint4 *>(a.cap_steps + (uint64_t)walk * 4u) = v;
   }
-  if (slot < n_block && r == 0) {
+  if (slot < n_block && r == 0 && !skip && (!kSv || finished)) {
     a.best_seq[walk * KW] = bestP.w0;
     if (KW > 1) a.best_seq[walk * KW + 1] = bestP.w1;
     if (KW > 2) a.best_seq[walk * KW + 2] = bestP.w2;
@@ -785,6 +864,10 @@ __device__ __forceinline__ void run_full_block(const FullTask &a, uint8_t *lds) 
     a.best_E[walk] = bestE;
     a.steps_done[walk] = steps;
     if (a.digest) a.digest[walk] = mix64(h ^ (uint64_t)steps);
+  }
+  if (kSv && a.done_flag) {
+    const int all = __syncthreads_and((slot >= n_block || skip || finished) ? 1 : 0);
+    if (threadIdx.x == 0 && all) __hip_atomic_store(a.done_flag, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
   }
 }
 
@@ -810,6 +893,11 @@ __global__ void __launch_bounds__(kBlock, FullOccupancy<NW>::value) full_walk_ke
   t.tables = w.tables + (uint64_t)first * w.table_bytes;
   t.table_bytes = w.table_bytes;
   t.n_buckets = w.n_buckets;
+  t.state = nullptr;
+  t.wstat = nullptr;
+  t.step_end = w.walk_len;
+  t.preempt = nullptr;
+  t.done_flag = nullptr;
   run_full_block<NW, entry_format(32 * (NW - 1) + 2), ClassCodes<NW, NW>>(t, lds);
 }
 
@@ -823,14 +911,18 @@ __global__ void __launch_bounds__(kBlock, FullOccupancy<NW>::value) full_walk_ke
 template <int NHI>
 struct FullBatchOccupancy { static constexpr int value = NHI <= 4 ? 3 : 2; };
 
-template <int NLO, int NHI>
+template <int NLO, int NHI, bool kSv>
 __global__ void __launch_bounds__(kBlock, FullBatchOccupancy<NHI>::value) full_batch_kernel(const BatchLaunch b) {
   extern __shared__ __align__(16) uint8_t lds[];
   __shared__ int64_t s_item;
   uint8_t *arena = b.arena + (uint64_t)blockIdx.x * b.arena_bytes;
   for (;;) {
     __syncthreads();                       // previous item finished, s_item consumed
-    if (threadIdx.x == 0) s_item = (int64_t)atomicAdd(b.counter, 1u);
+    if (threadIdx.x == 0) {
+      // no further item once the host has asked the launch to stop
+      s_item = (kSv && b.preempt && full_stop_requested(b.preempt)) ? b.n_items
+                                                                    : (int64_t)atomicAdd(b.counter, 1u);
+    }
     __syncthreads();
     const int64_t it = s_item;
     if (it >= b.n_items) break;            // uniform: every wave leaves together
@@ -854,7 +946,12 @@ __global__ void __launch_bounds__(kBlock, FullBatchOccupancy<NHI>::value) full_b
     t.tables = in.tables ? in.tables + (uint64_t)item.walk_begin * in.table_bytes : arena;
     t.table_bytes = in.table_bytes;
     t.n_buckets = in.n_buckets;
-    run_full_block<NHI, entry_format(NLO == 1 ? 3 : 32 * (NLO - 1) + 2), ClassCodes<NLO, NHI>>(t, lds);
+    t.state = in.state;
+    t.wstat = in.wstat;
+    t.step_end = in.step_end;
+    t.preempt = b.preempt;
+    t.done_flag = b.item_done ? b.item_done + it : nullptr;
+    run_full_block<NHI, entry_format(NLO == 1 ? 3 : 32 * (NLO - 1) + 2), ClassCodes<NLO, NHI>, kSv>(t, lds);
   }
 }
 
@@ -862,19 +959,19 @@ __global__ void __launch_bounds__(kBlock, FullBatchOccupancy<NHI>::value) full_b
 // largest one's kernel.
 __host__ __device__ constexpr int batch_group_of(int nw) { return nw <= 4 ? 4 : (nw <= 7 ? 7 : 8); }
 
-template <int NLO, int NHI>
+template <int NLO, int NHI, bool kSv>
 static hipError_t launch_batch_g(const BatchLaunch &b, int grid, hipStream_t stream) {
   const size_t lds = Geom<NHI>::lds_bytes();
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(full_batch_kernel<NLO, NHI>),
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(full_batch_kernel<NLO, NHI, kSv>),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((full_batch_kernel<NLO, NHI>), dim3((unsigned)grid), dim3(kBlock), lds, stream, b);
+  hipLaunchKernelGGL((full_batch_kernel<NLO, NHI, kSv>), dim3((unsigned)grid), dim3(kBlock), lds, stream, b);
   return hipGetLastError();
 }
 
-template <int NLO, int NHI>
+template <int NLO, int NHI, bool kSv>
 static hipError_t blocks_per_cu_g(int *blocks) {
-  const void *fn = reinterpret_cast<const void *>(full_batch_kernel<NLO, NHI>);
+  const void *fn = reinterpret_cast<const void *>(full_batch_kernel<NLO, NHI, kSv>);
   const size_t lds = Geom<NHI>::lds_bytes();
   hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
@@ -901,21 +998,35 @@ int full_lanes_per_walk() { return full::kG; }
 
 int full_batch_variant(int nw) { return full::batch_group_of(nw); }
 
-hipError_t full_batch_blocks_per_cu(int variant, int *blocks) {
+// The serving form of each group's kernel runs every shorter length too
+// (classes from 1 up): a serving launch is one grid on the kernel of the
+// largest group present.  Plain batches launch each group on its own kernel.
+template <bool kSv>
+static hipError_t full_blocks_per_cu_s(int variant, int *blocks) {
   switch (variant) {
-    case 4: return full::blocks_per_cu_g<1, 4>(blocks);
-    case 7: return full::blocks_per_cu_g<5, 7>(blocks);
-    default: return full::blocks_per_cu_g<8, 8>(blocks);
+    case 4: return full::blocks_per_cu_g<1, 4, kSv>(blocks);
+    case 7: return full::blocks_per_cu_g<kSv ? 1 : 5, 7, kSv>(blocks);
+    default: return full::blocks_per_cu_g<kSv ? 1 : 8, 8, kSv>(blocks);
   }
 }
 
-hipError_t launch_full_batch(const BatchLaunch &b, int variant, int grid, hipStream_t stream) {
-  if (grid <= 0) return hipSuccess;
+hipError_t full_batch_blocks_per_cu(int variant, int *blocks, bool serve) {
+  return serve ? full_blocks_per_cu_s<true>(variant, blocks) : full_blocks_per_cu_s<false>(variant, blocks);
+}
+
+template <bool kSv>
+static hipError_t launch_full_batch_s(const BatchLaunch &b, int variant, int grid, hipStream_t stream) {
   switch (variant) {
-    case 4: return full::launch_batch_g<1, 4>(b, grid, stream);
-    case 7: return full::launch_batch_g<5, 7>(b, grid, stream);
-    default: return full::launch_batch_g<8, 8>(b, grid, stream);
+    case 4: return full::launch_batch_g<1, 4, kSv>(b, grid, stream);
+    case 7: return full::launch_batch_g<kSv ? 1 : 5, 7, kSv>(b, grid, stream);
+    default: return full::launch_batch_g<kSv ? 1 : 8, 8, kSv>(b, grid, stream);
   }
+}
+
+hipError_t launch_full_batch(const BatchLaunch &b, int variant, int grid, hipStream_t stream, bool serve) {
+  if (grid <= 0) return hipSuccess;
+  return serve ? launch_full_batch_s<true>(b, variant, grid, stream)
+               : launch_full_batch_s<false>(b, variant, grid, stream);
 }
 
 size_t full_walk_lds_bytes(int32_t L) {

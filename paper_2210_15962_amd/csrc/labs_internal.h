@@ -54,8 +54,8 @@ struct WalkLaunch {
 // Progress of one walk between launches (continuous batching): the pivot, the
 // best so far, the digest chain, moves made, the predecessor and a stop flag.
 struct WalkState {
-  uint64_t P[3];
-  uint64_t bestP[3];
+  uint64_t P[4];            // skew-symmetric walks use up to three words
+  uint64_t bestP[4];
   uint64_t h;
   int64_t steps;
   int32_t bestE;
@@ -116,10 +116,10 @@ struct BatchLaunch {
 // Host helpers shared by labs_api.cpp and labs_serve.cpp.
 int32_t set_error(int32_t code, const char *fmt, ...);
 int32_t clear_error();
-// Visited-table geometry for walk_len moves at a load factor (false if the
-// table would not fit 32-bit bucket indices).
+// Visited-table geometry for walk_len moves at a load factor, skew-symmetric
+// or whole-space keys (false if the table would not fit 32-bit bucket indices).
 bool table_geometry(int32_t L, int64_t walk_len, double load_factor, uint32_t *n_buckets,
-                    uint64_t *table_bytes);
+                    uint64_t *table_bytes, bool full = false);
 // Lanes per walk and load factor from the tuning table (or the default).
 void tuned_plan(int32_t L, int32_t *lanes, double *load_factor);
 
@@ -139,8 +139,10 @@ hipError_t launch_full_walks(const WalkLaunch &w, hipStream_t stream);
 // Whole-space batches: kernel group of lag-word class nw (4: classes 1-4,
 // 7: classes 5-7, 8: class 8), resident workgroups per CU, and the launch.
 int full_batch_variant(int nw);
-hipError_t full_batch_blocks_per_cu(int variant, int *blocks);
-hipError_t launch_full_batch(const BatchLaunch &b, int variant, int grid, hipStream_t stream);
+// serve: the serving form (per-walk status, stop flag, item completion words).
+hipError_t full_batch_blocks_per_cu(int variant, int *blocks, bool serve = false);
+hipError_t launch_full_batch(const BatchLaunch &b, int variant, int grid, hipStream_t stream,
+                             bool serve = false);
 // Batch kernel of lag-word class nw (2..6; class 1 runs on the class-2 kernel).
 int batch_variant(int nw);
 size_t batch_lds_bytes(int variant);

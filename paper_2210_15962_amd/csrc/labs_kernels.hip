@@ -457,9 +457,11 @@ struct BlockTask {
   uint32_t *done_flag;      // batches: set to 1 if the block ends with every walk finished
 };
 
-// A nonzero stop word from the host (fine-grained memory: read past the caches).
+// A nonzero stop word from the host (fine-grained memory: read past the
+// caches).  One lane of the wave reads it, so a poll is one host-memory read.
 __device__ __forceinline__ bool stop_requested(const uint32_t *flag) {
-  const uint32_t v = __hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+  uint32_t v = 0u;
+  if (__lane_id() == 0) v = __hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
   return __builtin_amdgcn_readfirstlane(v) != 0u;
 }
 
@@ -1036,10 +1038,11 @@ __global__ void __launch_bounds__(kBlock) walk_kernel(const WalkLaunch w) {
 // the variant compiled for its lag-word class and lanes per walk.
 // ---------------------------------------------------------------------------
 
-// Waves per SIMD the batch kernel of a class is built for: classes up to 4
-// fit three (168 VGPRs), the longer ones two.
+// Waves per SIMD the batch kernel of a class is built for: three (168 VGPRs)
+// up to class 5 -- class 5 spills a few dwords there, and still runs the
+// 121..301 request mix 6 % faster than at two waves -- and two for class 6.
 template <int NWMAX>
-struct BatchOccupancy { static constexpr int value = NWMAX <= 4 ? 3 : 2; };
+struct BatchOccupancy { static constexpr int value = NWMAX <= 5 ? 3 : 2; };
 
 template <int NWMAX, bool kSv>
 __global__ void __launch_bounds__(kBlock, BatchOccupancy<NWMAX>::value) batch_kernel(const BatchLaunch b) {

@@ -137,7 +137,8 @@ constexpr int kHostFlagWords = 64;
 struct labs_server {
   int device = 0;
   hipStream_t stream = nullptr;
-  hipStream_t group_stream[8] = {nullptr};  // one per kernel class (2..6), default priority
+  hipStream_t kstream = nullptr;    // the launches (default priority)
+  bool full = false;                // whole-space requests (else skew-symmetric)
   uint8_t *pool = nullptr;          // control region, then request ranges
   uint64_t pool_bytes = 0;
   uint64_t ctl_bytes = 0;           // control region size
@@ -192,6 +193,12 @@ hipError_t finish(labs_server *s, Request *q) {
   if (e == hipSuccess) e = hipMemcpyAsync(q->h_dig.data(), b + q->o_dig, q->h_dig.size() * 8, hipMemcpyDeviceToHost, s->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
   return e;
+}
+
+// Batch kernel (class group) that runs length L on this server.
+int kernel_variant(const labs_server *s, int L) {
+  return s->full ? lsaw::full_batch_variant(lsaw::full_lag_words_for(L))
+                 : lsaw::batch_variant(lsaw::lag_words_for(L));
 }
 
 // Groups of `per` walks of q that still have an unfinished walk.
@@ -251,54 +258,41 @@ void run_worker(labs_server *s) {
     inst.clear();
     items.clear();
     budget.clear();
-    // One persistent launch per lag-word class present (each at the
-    // occupancy of its own kernel), largest class first.
+    // One persistent grid per launch, on the kernel of the largest class
+    // present (a shorter length runs exactly on a longer class's kernel).
+    // Grids of several classes on separate streams would run concurrently
+    // only if their streams sat on different hardware queues, which the
+    // runtime does not promise; a grid queued behind another starves its
+    // requests until the other ends.
     int cus = 256;
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, s->device);
-    // Classes whose kernels reach the same occupancy share one launch on the
-    // largest class's kernel (separate launches would only add tails).
-    int launch_v[8] = {0, 0, 2, 3, 4, 5, 6, 6};
-    {
-      int present[8] = {0};
-      for (Request *q : run) present[lsaw::batch_variant(lsaw::lag_words_for(q->L))] = 1;
-      int top = 0, top_occ = 0;
-      for (int v = 6; v >= 2; --v) {
-        if (!present[v]) continue;
-        int occ = 0;
-        if (lsaw::batch_blocks_per_cu(v, &occ, true) != hipSuccess) occ = 0;
-        if (top && occ <= top_occ) {
-          launch_v[v] = top;
-        } else {
-          top = v;
-          top_occ = occ;
-        }
-      }
-    }
-    auto class_launch = [&](int L) { return launch_v[lsaw::batch_variant(lsaw::lag_words_for(L))]; };
-    int64_t slots_v[8] = {0}, items4_v[8] = {0};
-    int lanes_v[8] = {4, 4, 4, 4, 4, 4, 4, 4};
-    for (Request *q : run) items4_v[class_launch(q->L)] += groups_left(*q, lsaw::kBlock / 4);
-    for (int v = 2; v <= 6; ++v) {
-      if (!items4_v[v]) continue;
-      int per_cu = 1;
-      (void)lsaw::batch_blocks_per_cu(v, &per_cu, true);
-      slots_v[v] = (int64_t)std::max(per_cu, 1) * cus;
-      // Lanes per walk for this launch (walk state and tables do not depend
-      // on it): a request's own choice if it has one, else 4 or 8.  Eight
-      // lanes cost about 20% more per walk step than four (the per-move work
-      // is shared by half as many candidates per lane), so they pay only
-      // where four leave resident workgroups idle.  Chunked launches run
-      // every item to the chunk's end, so what counts there is how well the
-      // items fill whole rounds of workgroups; launches that are stopped
-      // early keep every workgroup busy once the items outnumber them.
+    int variant = 0;
+    for (Request *q : run) variant = std::max(variant, kernel_variant(s, q->L));
+    int per_cu = 1;
+    if (s->full) (void)lsaw::full_batch_blocks_per_cu(variant, &per_cu, true);
+    else (void)lsaw::batch_blocks_per_cu(variant, &per_cu, true);
+    const int64_t slots = (int64_t)std::max(per_cu, 1) * cus;
+    int64_t items4 = 0;
+    for (Request *q : run) items4 += groups_left(*q, lsaw::kBlock / 4);
+    // Lanes per walk for this launch (walk state and tables do not depend on
+    // it): a request's own choice if it has one, else 4 or 8 (whole-space
+    // walks: always 4).  Eight lanes cost about 20% more per walk step than
+    // four (the per-move work is shared by half as many candidates per
+    // lane), so they pay only where four leave resident workgroups idle.
+    // Chunked launches run every item to the chunk's end, so what counts
+    // there is how well the items fill whole rounds of workgroups; launches
+    // that are stopped early keep every workgroup busy once the items fill
+    // the device.
+    int lanes_auto = 4;
+    if (!s->full) {
       if (preemptive) {
-        lanes_v[v] = 6 * items4_v[v] < 5 * slots_v[v] ? 8 : 4;
+        lanes_auto = 6 * items4 < 5 * slots ? 8 : 4;
       } else {
         auto fill = [&](int64_t n) {
-          const int64_t rounds = (n + slots_v[v] - 1) / slots_v[v];
-          return rounds > 0 ? (double)n / (double)(rounds * slots_v[v]) : 0.0;
+          const int64_t rounds = (n + slots - 1) / slots;
+          return rounds > 0 ? (double)n / (double)(rounds * slots) : 0.0;
         };
-        lanes_v[v] = 0.8 * fill(2 * items4_v[v]) > fill(items4_v[v]) ? 8 : 4;
+        lanes_auto = 0.8 * fill(2 * items4) > fill(items4) ? 8 : 4;
       }
     }
     hipError_t up_err = hipSuccess;           // first failing upload or clear, if any
@@ -334,7 +328,7 @@ void run_worker(labs_server *s) {
       d.wstat = b + q->o_wstat;
       d.step_end = preemptive ? q->walk_len : q->progress + take;
       inst.push_back(d);
-      const int lanes = q->lanes ? q->lanes : lanes_v[class_launch(q->L)];
+      const int lanes = q->lanes ? q->lanes : lanes_auto;
       const int per = lsaw::kBlock / lanes;
       for (int64_t w = 0; w < q->n_walks; w += per) {
         const int64_t n = std::min<int64_t>(per, q->n_walks - w);
@@ -343,19 +337,16 @@ void run_worker(labs_server *s) {
         if (!left) continue;                  // every walk of the group has finished
         lsaw::BatchItemDev it{};
         it.inst = (int32_t)k;
-        it.code = (lsaw::lag_words_for(q->L) << 4) | lanes;
+        it.code = ((s->full ? lsaw::full_lag_words_for(q->L) : lsaw::lag_words_for(q->L)) << 4) | lanes;
         it.n_walks = (int32_t)n;
         it.walk_begin = w;
         items.push_back(it);
       }
     }
-    // By class; then, in chunked launches, longest items first (cost grows
-    // with L, so each persistent grid ends on short items), else oldest
-    // request first (launches are cut short, so no grid tail to shape).
-    auto variant_of = [&](const lsaw::BatchItemDev &x) { return class_launch(inst[x.inst].L); };
+    // In chunked launches longest items first (cost grows with L, so the
+    // persistent grid ends on short items), else oldest request first
+    // (launches are cut short, so no grid tail to shape).
     std::stable_sort(items.begin(), items.end(), [&](const lsaw::BatchItemDev &x, const lsaw::BatchItemDev &y) {
-      const int vx = variant_of(x), vy = variant_of(y);
-      if (vx != vy) return vx > vy;
       return preemptive ? x.inst < y.inst : inst[x.inst].L > inst[y.inst].L;
     });
     uint8_t *ctl = s->pool;
@@ -382,25 +373,12 @@ void run_worker(labs_server *s) {
       e = hipMemcpyAsync(ctl + inst_off, inst.data(), inst.size() * sizeof(lsaw::BatchInstanceDev),
                          hipMemcpyHostToDevice, s->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(s->stream);   // work lists in place
-    bool used_v[8] = {false};
-    for (size_t g0 = 0; g0 < items.size() && e == hipSuccess;) {
-      const int v = variant_of(items[g0]);
-      size_t g1 = g0;
-      while (g1 < items.size() && variant_of(items[g1]) == v) ++g1;
-      lsaw::BatchLaunch bg = bl;
-      bg.items = bl.items + g0;
-      bg.n_items = (int64_t)(g1 - g0);
-      bg.item_done = bl.item_done + g0;
-      const int grid = (int)std::min<int64_t>(bg.n_items, slots_v[v]);
-      // Groups hold disjoint requests, so they run concurrently, each on its
-      // own stream with its own queue head: one group's tail overlaps the
-      // other's work.  Every workgroup only drains its own queue, so the
-      // grids finish whatever share of the GPU each gets.
-      bg.counter = reinterpret_cast<uint32_t *>(ctl) + 16 * v;
-      e = lsaw::launch_batch_reset(bg.counter, s->group_stream[v]);
-      if (e == hipSuccess) e = lsaw::launch_batch(bg, v, grid, s->group_stream[v], true);
-      used_v[v] = true;
-      g0 = g1;
+    if (e == hipSuccess && !items.empty()) {
+      const int grid = (int)std::min<int64_t>((int64_t)items.size(), slots);
+      e = lsaw::launch_batch_reset(bl.counter, s->kstream);
+      if (e == hipSuccess)
+        e = s->full ? lsaw::launch_full_batch(bl, variant, grid, s->kstream, true)
+                    : lsaw::launch_batch(bl, variant, grid, s->kstream, true);
     }
     if (preemptive && e == hipSuccess) {
       // Let the launch run until its walks finish, or ask it to stop (it then
@@ -411,14 +389,11 @@ void run_worker(labs_server *s) {
       int64_t t_check = 0;
       std::vector<int64_t> left(run.size(), 0);
       for (;;) {
-        bool busy = false;
-        for (int v = 2; v <= 6 && e == hipSuccess; ++v) {
-          if (!used_v[v]) continue;
-          const hipError_t qe = hipStreamQuery(s->group_stream[v]);
-          if (qe == hipErrorNotReady) busy = true;
-          else if (qe != hipSuccess) e = qe;
+        const hipError_t qe = hipStreamQuery(s->kstream);
+        if (qe != hipErrorNotReady) {
+          if (qe != hipSuccess) e = qe;
+          break;
         }
-        if (!busy || e != hipSuccess) break;
         if (!asked) {
           bool want = false;
           const int64_t t = now_ns();
@@ -441,8 +416,7 @@ void run_worker(labs_server *s) {
         if (asked) std::this_thread::sleep_for(std::chrono::microseconds(100));
       }
     }
-    for (int v = 2; v <= 6; ++v)
-      if (used_v[v] && e == hipSuccess) e = hipStreamSynchronize(s->group_stream[v]);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->kstream);
     const int64_t t1 = now_ns();
     // Items that ended with every walk finished, from the completion words.
     for (size_t i = 0; i < items.size() && e == hipSuccess; ++i) {
@@ -525,7 +499,13 @@ int32_t labs_serve_create(const labs_serve_cfg *cfg, labs_server **server) {
     return lsaw::set_error(LABS_EINVAL, "lanes_per_walk=%d: use 0, 2, 4 or 8", c.lanes_per_walk);
   if (c.load_factor != 0.0 && !(c.load_factor > 0.0 && c.load_factor <= 0.9))
     return lsaw::set_error(LABS_EINVAL, "load_factor=%g: use 0 or a value in (0, 0.9]", c.load_factor);
+  if (c.whole_space != 0 && c.whole_space != 1)
+    return lsaw::set_error(LABS_EINVAL, "whole_space=%d: use 0 or 1", c.whole_space);
+  if (c.whole_space && c.lanes_per_walk != 0 && c.lanes_per_walk != lsaw::full_lanes_per_walk())
+    return lsaw::set_error(LABS_EINVAL, "lanes_per_walk=%d: whole-space walks use 0 or %d", c.lanes_per_walk,
+                           lsaw::full_lanes_per_walk());
   labs_server *s = new labs_server();
+  s->full = c.whole_space != 0;
   s->max_pending = c.max_pending ? c.max_pending : 4096;
   s->lanes = c.lanes_per_walk;
   s->chunk = c.chunk_steps;
@@ -548,12 +528,10 @@ int32_t labs_serve_create(const labs_serve_cfg *cfg, labs_server **server) {
   if (e == hipSuccess)
     e = hipHostGetDevicePointer(reinterpret_cast<void **>(&s->dev_words), s->host_words, 0);
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking);
-  for (int v = 2; v <= 6 && e == hipSuccess; ++v)
-    e = hipStreamCreateWithFlags(&s->group_stream[v], hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->kstream, hipStreamNonBlocking);
   if (e != hipSuccess) {
     if (s->stream) (void)hipStreamDestroy(s->stream);
-    for (int v = 2; v <= 6; ++v)
-      if (s->group_stream[v]) (void)hipStreamDestroy(s->group_stream[v]);
+    if (s->kstream) (void)hipStreamDestroy(s->kstream);
     if (s->pool) (void)hipFree(s->pool);
     if (s->host_words) (void)hipHostFree(s->host_words);
     delete s;
@@ -578,8 +556,7 @@ int32_t labs_serve_destroy(labs_server *s) {
   if (s->worker.joinable()) s->worker.join();
   for (auto &kv : s->all) delete kv.second;
   if (s->stream) (void)hipStreamDestroy(s->stream);
-  for (int v = 2; v <= 6; ++v)
-    if (s->group_stream[v]) (void)hipStreamDestroy(s->group_stream[v]);
+  if (s->kstream) (void)hipStreamDestroy(s->kstream);
   if (s->pool) (void)hipFree(s->pool);
   if (s->host_words) (void)hipHostFree(s->host_words);
   delete s;
@@ -590,20 +567,21 @@ int32_t labs_serve_submit(labs_server *s, int32_t L, int64_t n_walks, int64_t wa
                           const uint64_t *starts, uint64_t *req_id) {
   if (!s || !req_id) return lsaw::set_error(LABS_EINVAL, "NULL server or req_id");
   if (n_walks <= 0) return lsaw::set_error(LABS_EINVAL, "n_walks=%lld must be > 0", (long long)n_walks);
-  const int32_t lanes = s->lanes;                 // 0: chosen per launch
+  const int32_t lanes = s->full ? lsaw::full_lanes_per_walk() : s->lanes;   // 0: chosen per launch
+  if (s->full ? !(L >= 3 && L <= lsaw::kFullLMax) : !(L >= 3 && L <= lsaw::kLMax && (L & 1)))
+    return lsaw::set_error(LABS_EINVAL, s->full ? "L=%d: need 3 <= L <= %d" : "L=%d: need odd L with 3 <= L <= %d",
+                           L, s->full ? lsaw::kFullLMax : lsaw::kLMax);
   double lf = s->load_factor;
   if (lf == 0.0) {
     int32_t tl = 4;
     double tf = 0.5;
-    if (L >= 3 && L <= lsaw::kLMax && (L & 1)) lsaw::tuned_plan(L, &tl, &tf);
+    if (!s->full) lsaw::tuned_plan(L, &tl, &tf);
     lf = tf;
   }
   uint32_t nb = 0;
   uint64_t tb = 0;
-  if (!(L >= 3 && L <= lsaw::kLMax && (L & 1)))
-    return lsaw::set_error(LABS_EINVAL, "L=%d: need odd L with 3 <= L <= %d", L, lsaw::kLMax);
   if (walk_len < 0) return lsaw::set_error(LABS_EINVAL, "walk_len must be >= 0");
-  if (!lsaw::table_geometry(L, walk_len, lf, &nb, &tb)) return LABS_EINVAL;
+  if (!lsaw::table_geometry(L, walk_len, lf, &nb, &tb, s->full)) return LABS_EINVAL;
   Request *q = new Request();
   q->L = L;
   q->n_walks = n_walks;
@@ -612,15 +590,15 @@ int32_t labs_serve_submit(labs_server *s, int32_t L, int64_t n_walks, int64_t wa
   q->lanes = lanes;
   q->n_buckets = nb;
   q->table_bytes = tb;
-  q->W = lsaw::key_words_for(L);
+  q->W = s->full ? lsaw::full_key_words_for(L) : lsaw::key_words_for(L);
   if (starts) {
     q->starts.assign(starts, starts + (size_t)n_walks * q->W);
-    const int D = lsaw::free_bits(L);
-    const int top = D - 64 * (q->W - 1);
+    const int bits = s->full ? L : lsaw::free_bits(L);   // key bits
+    const int top = bits - 64 * (q->W - 1);
     for (int64_t w = 0; w < n_walks; ++w)
       if (top < 64 && (q->starts[(size_t)w * q->W + q->W - 1] >> top) != 0) {
         delete q;
-        return lsaw::set_error(LABS_EINVAL, "start %lld has bits above D=%d", (long long)w, D);
+        return lsaw::set_error(LABS_EINVAL, "start %lld has bits above the %d key bits", (long long)w, bits);
       }
   }
   q->bytes = footprint(*q);

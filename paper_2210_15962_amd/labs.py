@@ -67,7 +67,7 @@ class SolveResult(ctypes.Structure):
 
 class ServeCfg(ctypes.Structure):
     _fields_ = [("pool_bytes", U64), ("max_pending", I32), ("lanes_per_walk", I32),
-                ("chunk_steps", I64), ("load_factor", ctypes.c_double)]
+                ("chunk_steps", I64), ("load_factor", ctypes.c_double), ("whole_space", I32)]
 
 
 class ServeResult(ctypes.Structure):
@@ -447,7 +447,9 @@ def make_instances(specs, results):
 
 
 def batch_workspace_bytes(specs, results=None) -> int:
-    results = results or [_alloc_outputs(sp["L"], 0, 0, 0) for sp in specs]
+    """labs_batch_workspace_bytes for the instances (output buffers of their
+    size are allocated for the call when results is None)."""
+    results = results or [_alloc_outputs(sp["L"], sp["n_walks"], 0, 0) for sp in specs]
     arr = make_instances(specs, results)
     b = U64(0)
     _check(lib().labs_batch_workspace_bytes(arr, len(specs), ctypes.byref(b)))
@@ -472,8 +474,10 @@ def walks_batch(specs, workspace=None, stream=None, device="cuda"):
     return results
 
 
-def full_batch_workspace_bytes(specs) -> int:
-    results = [_alloc_outputs(sp["L"], 0, 0, 0, full=True) for sp in specs]
+def full_batch_workspace_bytes(specs, results=None) -> int:
+    """labs_full_batch_workspace_bytes for whole-space instances (as
+    batch_workspace_bytes)."""
+    results = results or [_alloc_outputs(sp["L"], sp["n_walks"], 0, 0, full=True) for sp in specs]
     arr = make_instances(specs, results)
     b = U64(0)
     _check(lib().labs_full_batch_workspace_bytes(arr, len(specs), ctypes.byref(b)))
@@ -590,21 +594,24 @@ class Server:
 
     submit() queues one request and returns its id; poll()/wait() return None
     while it runs and a dict of host arrays (best_seq, best_E, steps_done,
-    digest) plus submit/admit/done times once it is done.
+    digest) plus submit/admit/done times once it is done.  whole_space=True
+    makes a server of whole-space requests (keys as for full_walks).
     """
 
     def __init__(self, pool_bytes: int = 0, max_pending: int = 0, lanes_per_walk: int = 0,
-                 chunk_steps: int = 0, load_factor: float = 0.0):
-        cfg = ServeCfg(pool_bytes, max_pending, lanes_per_walk, chunk_steps, load_factor)
+                 chunk_steps: int = 0, load_factor: float = 0.0, whole_space: bool = False):
+        cfg = ServeCfg(pool_bytes, max_pending, lanes_per_walk, chunk_steps, load_factor,
+                       1 if whole_space else 0)
         h = VP()
         _check(lib().labs_serve_create(ctypes.byref(cfg), ctypes.byref(h)))
         self._h = h
         self._shape = {}
+        self._key_words = full_key_words if whole_space else key_words
 
     def submit(self, L: int, n_walks: int, walk_len: int, seed: int = 0, starts=None) -> int:
         st = None
         if starts is not None:
-            st = np.ascontiguousarray(np.asarray(starts, dtype=np.uint64).reshape(n_walks, key_words(L)))
+            st = np.ascontiguousarray(np.asarray(starts, dtype=np.uint64).reshape(n_walks, self._key_words(L)))
         rid = U64(0)
         _check(lib().labs_serve_submit(self._h, L, n_walks, walk_len, seed,
                                        None if st is None else st.ctypes.data, ctypes.byref(rid)))
@@ -613,7 +620,7 @@ class Server:
 
     def _result(self, rid, call):
         L, n = self._shape.get(rid, (3, 0))      # unknown ids: the library reports them
-        W = key_words(L)
+        W = self._key_words(L)
         out = dict(best_seq=np.zeros((n, W), np.uint64), best_E=np.zeros(n, np.int32),
                    steps_done=np.zeros(n, np.int64), digest=np.zeros(n, np.uint64))
         res = ServeResult(out["best_seq"].ctypes.data, out["best_E"].ctypes.data,

@@ -178,6 +178,9 @@ def test_serve_validation_before_any_device_call():
                 labs.ServeCfg(0, 0, 0, -5, 0.0), labs.ServeCfg(0, 0, 0, 0, 0.95)]:
         assert lib.labs_serve_create(ctypes.byref(cfg), ctypes.byref(h)) == labs.LABS_EINVAL
         assert not h.value
+    for cfg in [labs.ServeCfg(0, 0, 0, 0, 0.0, 2), labs.ServeCfg(0, 0, 8, 0, 0.0, 1)]:
+        assert lib.labs_serve_create(ctypes.byref(cfg), ctypes.byref(h)) == labs.LABS_EINVAL   # whole space: 0/1, 4 lanes
+        assert not h.value
     rid = labs.U64(0)
     assert lib.labs_serve_submit(None, 27, 1, 1, 0, None, ctypes.byref(rid)) == labs.LABS_EINVAL
     assert lib.labs_serve_poll(None, 1, None) == labs.LABS_EINVAL

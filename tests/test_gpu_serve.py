@@ -195,3 +195,43 @@ def test_destroy_with_work_in_flight():
     time.sleep(0.05)
     srv.close()                                           # returns after the current launch
     srv.close()
+
+
+@pytest.mark.parametrize("chunk", [0, 700])
+def test_whole_space_server_matches_standalone_and_oracle(chunk):
+    """A whole-space server (whole_space=True): requests of odd and even L
+    across the three kernel groups, with spread arrivals, explicit starts and
+    an empty walk; every request equals its standalone labs_full_walks run,
+    and the oracle on its first walks."""
+    labs = _labs()
+    reqs = [dict(L=L, n=n, walk_len=wl, seed=70 + i)
+            for i, (L, n, wl) in enumerate([(20, 96, 2500), (64, 130, 1800), (128, 64, 1500),
+                                            (150, 70, 900), (200, 40, 700), (255, 33, 500)])]
+    reqs.append(dict(L=50, n=8, walk_len=0, seed=3))
+    keys = I.random_full_keys(97, 24, seed=9)
+    reqs.append(dict(L=97, n=24, walk_len=1200, seed=0, starts=keys))
+    with labs.Server(pool_bytes=POOL, chunk_steps=chunk, whole_space=True) as srv:
+        ids = []
+        for i, q in enumerate(reqs):
+            ids.append(srv.submit(q["L"], q["n"], q["walk_len"], q["seed"], q.get("starts")))
+            if i % 2 == 1:
+                time.sleep(0.02)
+        out = [srv.wait(rid, timeout_s=120) for rid in ids]
+        st = srv.stats()
+        with pytest.raises(labs.LabsError) as e:
+            srv.submit(256, 4, 10)                        # whole space: L <= 255
+        assert e.value.code == labs.LABS_EINVAL
+    for q, r in zip(reqs, out):
+        assert r is not None
+        st_t = None if "starts" not in q else torch.from_numpy(I.as_int64_keys(q["starts"])).cuda()
+        alone = labs.full_walks(q["L"], q["n"], q["walk_len"], seed=q["seed"], starts_t=st_t)
+        torch.cuda.synchronize()
+        alone = {k: v.cpu().numpy() for k, v in alone.items() if v is not None}
+        _assert_same(r, alone)
+    for q, r in [(reqs[0], out[0]), (reqs[4], out[4]), (reqs[-1], out[-1])]:
+        starts = q["starts"] if "starts" in q else O.full_starts(q["L"], 2, q["seed"])
+        for i in range(2):
+            o = O.full_walk(q["L"], starts[i], q["walk_len"])
+            assert r["best_E"][i] == o.best_E and r["digest"][i] == o.digest
+            assert r["steps_done"][i] == o.steps
+    assert st["completed"] == len(reqs) and st["pool_used"] == 0
