@@ -6,7 +6,7 @@ from seeded uniform starts).  Prints one JSON line with walk steps/s (Sum of
 steps_done over the timed steps / time), neighbour evaluations/s, the INT32
 VALU roofline of the walk kernel, the served stream (p50/p99 latency and
 served vs plain-batch steps/s at 10 and 200 req/s) and the CPU oracle baseline.
-Other workloads run alone under their flags (--full, --paper-regime,
+Other workloads run alone under their flags (--full, --full-batch, --paper-regime,
 --mixed-batch, --serve-sweep, --solve-target).
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
@@ -385,6 +385,56 @@ def run_mixed_batch(steps: int, warmup: int, autotune: bool):
             "distinct_L": len(set(Ls))}
 
 
+def run_full_batch(steps: int, warmup: int):
+    """Whole-space mixed-length batch: 128 instances, L uniform over [64, 255]
+    (every length, odd or even), 1,024 walks x 8,192 moves each, instance i
+    seeded with i; one labs_full_walks_batch call per step, timed with HIP
+    events on the launch stream, the workspace allocated beforehand."""
+    import torch
+    import labs_inputs as I
+    from paper_2210_15962_amd import labs
+    Ls = [int(L) for L in I.lengths(128, 64, 255, seed=0)]
+    specs = [dict(L=L, n_walks=1024, walk_len=8192, seed=i, cap_steps=True) for i, L in enumerate(Ls)]
+    ws = labs.alloc_workspace(labs.full_batch_workspace_bytes(specs))
+    stream = torch.cuda.current_stream()
+    for _ in range(warmup):
+        labs.full_walks_batch(specs, workspace=ws)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ms, total, alg = 0.0, 0, 0
+    caps_all = [0, 0, 0, 0]
+    t0 = time.perf_counter()
+    results = []
+    for _ in range(steps):
+        ev0.record(stream)
+        res = labs.full_walks_batch(specs, workspace=ws)
+        ev1.record(stream)
+        ev1.synchronize()
+        ms += ev0.elapsed_time(ev1)
+        results.append(res)
+    wall = time.perf_counter() - t0
+    for res in results:
+        for L, r in zip(Ls, res):
+            total += int(r["steps_done"].sum().item())
+            c = r["cap_steps"].sum(0).cpu().numpy()
+            alg += sum(int(c[k]) * full_ops_per_scan(L, cap) for k, cap in enumerate(CAPS))
+            caps_all = [caps_all[k] + int(c[k]) for k in range(4)]
+    del ws
+    torch.cuda.empty_cache()
+    achieved = alg / (ms / 1e3)
+    return {"workload": "whole space, 128 instances, L uniform in [64, 255], 1024 walks x 8192 moves, "
+                        "persistent launches per class group",
+            "steps_per_s": total / wall, "steps_per_s_events": total / (ms / 1e3),
+            "ms_per_step": ms / steps, "steps": steps,
+            "neighbour_evals_per_s": sum(int(r["steps_done"].sum().item()) * L for L, r in zip(Ls, results[-1]))
+                                     / (ms / steps / 1e3),
+            "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": INT32_VALU_PEAK / 1e12,
+                         "unit": "TOP/s", "frac": achieved / INT32_VALU_PEAK, "traffic": None,
+                         "kernel": f"full_batch_kernel@{kernel_source_tag('labs_full.hip')}",
+                         "alg_ops_per_step": alg / steps,
+                         "scans_by_plane_cap": {str(c or "all"): v for c, v in zip(CAPS, caps_all)}}}
+
+
 def run_solve_target(L: int, target: int, time_limit: float, walks: int, seed: int):
     """Alg. 1 driver until E <= target (a Table 1 energy) or the time limit:
     time-to-target and NFEs-to-target against the lambda model's mean 1/lambda."""
@@ -472,6 +522,8 @@ def main():
     ap.add_argument("--paper-regime", type=str, default="",
                     help="comma-separated L: rounds of fresh 8D-move walks (Sec. 4) only")
     ap.add_argument("--paper-walks", type=int, default=262144)
+    ap.add_argument("--full-batch", action="store_true",
+                    help="whole-space mixed-length batch (128 instances, L in [64, 255]) only")
     ap.add_argument("--mixed-batch", action="store_true",
                     help="256-instance mixed-L batch (hipGraph replays) only, default then autotuned")
     ap.add_argument("--no-autotune", action="store_true",
@@ -503,6 +555,10 @@ def main():
         for r in run_paper_regime([int(x) for x in args.paper_regime.split(",")], args.paper_walks,
                                   args.steps, args.warmup):
             print(json.dumps(r), flush=True)
+        return
+
+    if args.full_batch:
+        print(json.dumps(run_full_batch(args.steps, args.warmup)), flush=True)
         return
 
     if args.mixed_batch:

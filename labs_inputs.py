@@ -61,6 +61,11 @@ def odd_lengths(n: int, lo: int, hi: int, seed: int) -> np.ndarray:
     return lo + 2 * _rng(seed).integers(0, k, size=n)
 
 
+def lengths(n: int, lo: int, hi: int, seed: int) -> np.ndarray:
+    """n lengths drawn uniformly from {lo, lo+1, ..., hi}."""
+    return lo + _rng(seed).integers(0, hi - lo + 1, size=n)
+
+
 def poisson_arrivals(rate: float, n: int, seed: int) -> np.ndarray:
     """Arrival times (seconds) of n requests of a Poisson process of the given rate."""
     u = _rng(seed).random(n)
