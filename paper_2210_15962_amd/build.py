@@ -37,7 +37,7 @@ def build(verbose: bool = True) -> str:
         extra = ["-save-temps=obj"]
     # The device translation units compile in parallel (the walk kernels take minutes).
     procs = []
-    for src in ("labs_kernels.hip", "labs_full.hip", "labs_noalloc.hip"):
+    for src in ("labs_kernels.hip", "labs_full.hip", "labs_full_serve.hip", "labs_noalloc.hip"):
         obj = os.path.join(bdir, src.replace(".hip", ".o"))
         cmd = [hipcc, "-x", "hip", f"--offload-arch={ARCH}", *COMMON, *DEVICE_FLAGS, *extra, "-c",
                os.path.join(CSRC, src), "-o", obj]

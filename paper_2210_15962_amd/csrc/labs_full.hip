@@ -994,10 +994,6 @@ static hipError_t launch_nw(const WalkLaunch &w, hipStream_t stream) {
 
 }  // namespace full
 
-int full_lanes_per_walk() { return full::kG; }
-
-int full_batch_variant(int nw) { return full::batch_group_of(nw); }
-
 // The serving form of each group's kernel runs every shorter length too
 // (classes from 1 up): a serving launch is one grid on the kernel of the
 // largest group present.  Plain batches launch each group on its own kernel.
@@ -1010,9 +1006,6 @@ static hipError_t full_blocks_per_cu_s(int variant, int *blocks) {
   }
 }
 
-hipError_t full_batch_blocks_per_cu(int variant, int *blocks, bool serve) {
-  return serve ? full_blocks_per_cu_s<true>(variant, blocks) : full_blocks_per_cu_s<false>(variant, blocks);
-}
 
 template <bool kSv>
 static hipError_t launch_full_batch_s(const BatchLaunch &b, int variant, int grid, hipStream_t stream) {
@@ -1023,10 +1016,32 @@ static hipError_t launch_full_batch_s(const BatchLaunch &b, int variant, int gri
   }
 }
 
+#ifdef LABS_FULL_SERVING_ONLY
+// labs_full_serve.hip: the serving forms, compiled in a translation unit of
+// their own (in parallel with this one).
+hipError_t full_serving_blocks_per_cu(int variant, int *blocks) {
+  return full_blocks_per_cu_s<true>(variant, blocks);
+}
+
+hipError_t launch_full_serving(const BatchLaunch &b, int variant, int grid, hipStream_t stream) {
+  return launch_full_batch_s<true>(b, variant, grid, stream);
+}
+#else
+// Serving forms (labs_full_serve.hip).
+hipError_t full_serving_blocks_per_cu(int variant, int *blocks);
+hipError_t launch_full_serving(const BatchLaunch &b, int variant, int grid, hipStream_t stream);
+
+int full_lanes_per_walk() { return full::kG; }
+
+int full_batch_variant(int nw) { return full::batch_group_of(nw); }
+
+hipError_t full_batch_blocks_per_cu(int variant, int *blocks, bool serve) {
+  return serve ? full_serving_blocks_per_cu(variant, blocks) : full_blocks_per_cu_s<false>(variant, blocks);
+}
+
 hipError_t launch_full_batch(const BatchLaunch &b, int variant, int grid, hipStream_t stream, bool serve) {
   if (grid <= 0) return hipSuccess;
-  return serve ? launch_full_batch_s<true>(b, variant, grid, stream)
-               : launch_full_batch_s<false>(b, variant, grid, stream);
+  return serve ? launch_full_serving(b, variant, grid, stream) : launch_full_batch_s<false>(b, variant, grid, stream);
 }
 
 size_t full_walk_lds_bytes(int32_t L) {
@@ -1057,5 +1072,6 @@ hipError_t launch_full_walks(const WalkLaunch &w, hipStream_t stream) {
     default: return hipErrorInvalidValue;
   }
 }
+#endif
 
 }  // namespace lsaw
