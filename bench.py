@@ -7,7 +7,7 @@ steps_done over the timed steps / time), neighbour evaluations/s, the INT32
 VALU roofline of the walk kernel, the served stream (p50/p99 latency and
 served vs plain-batch steps/s at 10 and 200 req/s) and the CPU oracle baseline.
 Other workloads run alone under their flags (--full, --full-batch, --paper-regime,
---mixed-batch, --serve-sweep, --solve-target).
+--mixed-batch, --serve-sweep, --serve-full-sweep, --solve-target).
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
 """
@@ -249,34 +249,40 @@ def run_full(L: int, n: int, walk_len: int, steps: int, warmup: int, cpu: bool, 
     return out
 
 
-def serve_workload(n_req: int, rate: float, seed: int = 0):
-    """Served stream: Poisson arrivals, L uniform odd in [121, 301], 4096 walks
-    x 65,536 moves per request from seeded starts."""
+# Served streams: skew-symmetric requests (L odd in [121, 301], 4,096 walks x
+# 65,536 moves) or whole-space requests (L in [64, 255], 4,096 walks x 16,384
+# moves), both from seeded starts.
+SERVE_SKEW = dict(lo=121, hi=301, n_walks=4096, walk_len=65536, seed_base=10_000)
+SERVE_FULL = dict(lo=64, hi=255, n_walks=4096, walk_len=16384, seed_base=20_000)
+
+
+def serve_workload(n_req: int, rate: float, seed: int = 0, full: bool = False):
+    """Served stream: Poisson arrivals at `rate`, L uniform over the stream's
+    range (odd lengths for skew-symmetric requests, every length for
+    whole-space ones)."""
     import labs_inputs as I
-    Ls = I.odd_lengths(n_req, 121, 301, seed=seed)
+    w = SERVE_FULL if full else SERVE_SKEW
+    Ls = (I.lengths if full else I.odd_lengths)(n_req, w["lo"], w["hi"], seed=seed)
     t = I.poisson_arrivals(rate, n_req, seed=seed + 1)
-    return [dict(L=int(L), n_walks=4096, walk_len=65536, seed=10_000 + i, t_arrive=float(t[i]))
-            for i, L in enumerate(Ls)]
+    return [dict(L=int(L), n_walks=w["n_walks"], walk_len=w["walk_len"], seed=w["seed_base"] + i,
+                 t_arrive=float(t[i])) for i, L in enumerate(Ls)]
 
 
-def run_plain_batch(n_req: int, load_factor: float):
-    """The served stream's requests as one plain mixed-L batch (one persistent
-    launch); the workspace is allocated before the timed region."""
-    import ctypes
+def run_plain_batch(n_req: int, load_factor: float, full: bool = False):
+    """The served stream's requests as one plain mixed-L batch (persistent
+    launches); the workspace is allocated before the timed region."""
     import torch
     from paper_2210_15962_amd import labs
-    reqs = serve_workload(n_req, 1.0)
+    reqs = serve_workload(n_req, 1.0, full=full)
     specs = [dict(L=q["L"], n_walks=q["n_walks"], walk_len=q["walk_len"], seed=q["seed"],
                   load_factor=load_factor) for q in reqs]
-    outs = [labs._alloc_outputs(sp["L"], sp["n_walks"], sp["walk_len"], 0) for sp in specs]
-    nb = labs.U64(0)
-    labs._check(labs.lib().labs_batch_workspace_bytes(labs.make_instances(specs, outs), len(specs),
-                                                      ctypes.byref(nb)))
-    ws = labs.alloc_workspace(nb.value)
-    del outs
+    if full:
+        ws = labs.alloc_workspace(labs.full_batch_workspace_bytes(specs))
+    else:
+        ws = labs.alloc_workspace(labs.batch_workspace_bytes(specs))
     torch.cuda.synchronize()
     tb = time.perf_counter()
-    out = labs.walks_batch(specs, workspace=ws)
+    out = (labs.full_walks_batch if full else labs.walks_batch)(specs, workspace=ws)
     torch.cuda.synchronize()
     tb = time.perf_counter() - tb
     bsteps = int(sum(int(o["steps_done"].sum().item()) for o in out))
@@ -287,18 +293,19 @@ def run_plain_batch(n_req: int, load_factor: float):
 
 
 def run_serving(n_req: int, rate: float, load_factor: float, chunk: int, batch=None,
-                pool_frac: float = 0.85):
-    """Serve the stream through labs_serve_* (Poisson arrivals at `rate`) and
-    compare with the same requests as one plain batch; returns latency
-    percentiles and both throughputs."""
+                pool_frac: float = 0.85, full: bool = False):
+    """Serve the stream through labs_serve_* (Poisson arrivals at `rate`; a
+    whole-space server when `full`) and compare with the same requests as one
+    plain batch; returns latency percentiles and both throughputs."""
     import numpy as np
     import torch
     from paper_2210_15962_amd import labs
-    reqs = serve_workload(n_req, rate)
-    batch_rate, bsteps, bdig = batch if batch is not None else run_plain_batch(n_req, load_factor)
+    w = SERVE_FULL if full else SERVE_SKEW
+    reqs = serve_workload(n_req, rate, full=full)
+    batch_rate, bsteps, bdig = batch if batch is not None else run_plain_batch(n_req, load_factor, full)
     free, _ = torch.cuda.mem_get_info()
     pool = int(free * pool_frac)
-    with labs.Server(pool_bytes=pool, load_factor=load_factor, chunk_steps=chunk) as srv:
+    with labs.Server(pool_bytes=pool, load_factor=load_factor, chunk_steps=chunk, whole_space=full) as srv:
         ids = []
         t0 = time.perf_counter()
         for q in reqs:
@@ -313,14 +320,15 @@ def run_serving(n_req: int, rate: float, load_factor: float, chunk: int, batch=N
     span = (max(r["t_done_ns"] for r in res) - min(r["t_submit_ns"] for r in res)) / 1e9
     served = steps / span
     same = all(np.array_equal(r["digest"], d.view(np.uint64)) for r, d in zip(res, bdig))
-    return {"rate_req_per_s": rate, "requests": n_req, "walks_per_request": 4096,
-            "moves_per_walk": 65536, "L_range": [121, 301], "chunk_steps": chunk,
+    return {"rate_req_per_s": rate, "requests": n_req, "whole_space": full,
+            "walks_per_request": w["n_walks"], "moves_per_walk": w["walk_len"], "L_range": [w["lo"], w["hi"]],
+            "chunk_steps": chunk,
             "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
             "served_steps_per_s": served, "served_busy_steps_per_s": steps / (st["busy_ns"] / 1e9),
             "batch_steps_per_s": batch_rate, "served_over_batch": served / batch_rate,
             "launches": st["launches"], "pool_gib": st["pool_bytes"] / 2**30,
             "pool_peak_gib": st["pool_peak"] / 2**30,
-            "offered_over_capacity": rate * 4096 * 65536 / batch_rate,
+            "offered_over_capacity": rate * w["n_walks"] * w["walk_len"] / batch_rate,
             "served_equals_batch": bool(same and steps == bsteps)}
 
 
@@ -510,6 +518,9 @@ def main():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--serve-sweep", type=str, default="",
                     help="comma-separated arrival rates: serve only, one JSON line per rate")
+    ap.add_argument("--serve-full-sweep", type=str, default="",
+                    help="as --serve-sweep for a whole-space server (L in [64, 255], 4096 walks x "
+                         "16384 moves per request)")
     ap.add_argument("--solve-target", type=str, default="",
                     help="L:E -- Alg. 1 driver until E or --solve-time-limit (time-to-target)")
     ap.add_argument("--solve-time-limit", type=float, default=600.0)
@@ -567,11 +578,12 @@ def main():
             print(json.dumps(run_mixed_batch(args.steps, args.warmup, tune)), flush=True)
         return
 
-    if args.serve_sweep:
-        batch = run_plain_batch(args.serve_requests, args.load_factor)
-        for rate in [float(x) for x in args.serve_sweep.split(",")]:
+    if args.serve_sweep or args.serve_full_sweep:
+        full = bool(args.serve_full_sweep)
+        batch = run_plain_batch(args.serve_requests, args.load_factor, full)
+        for rate in [float(x) for x in (args.serve_full_sweep or args.serve_sweep).split(",")]:
             print(json.dumps(run_serving(args.serve_requests, rate, args.load_factor, args.serve_chunk,
-                                         batch=batch)), flush=True)
+                                         batch=batch, full=full)), flush=True)
         return
 
     L, n = WORKLOAD["L"], WORKLOAD["n_walks"]
