@@ -101,10 +101,14 @@ def full_ops_per_scan(L: int, cap: int = 0) -> int:
 
 
 def kernel_source_tag(name: str = "labs_kernels.hip") -> str:
+    """sha1 prefix of a kernel source together with the device headers it
+    includes (a change to any of them changes the kernel)."""
     import hashlib
-    src = os.path.join(ROOT, "paper_2210_15962_amd", "csrc", name)
-    with open(src, "rb") as f:
-        return hashlib.sha1(f.read()).hexdigest()[:12]
+    h = hashlib.sha1()
+    for part in (name, "labs_device.h", "labs_internal.h"):
+        with open(os.path.join(ROOT, "paper_2210_15962_amd", "csrc", part), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:12]
 
 
 def load_counter_traffic(kernel_tag: str, name: str = "walk_kernel_L151_traffic.json"):
