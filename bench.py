@@ -514,7 +514,7 @@ def main():
     ap.add_argument("--calibration-copy-mib", type=int, default=0,
                     help="run one plain device copy of this size first (counter calibration)")
     ap.add_argument("--serve-requests", type=int, default=64)
-    ap.add_argument("--serve-rates", type=str, default="10,200",
+    ap.add_argument("--serve-rates", type=str, default="10,25,200",
                     help="arrival rates (req/s) of the serving legs in the default run")
     ap.add_argument("--serve-chunk", type=int, default=0,
                     help="moves per launch per request (0: launches end when a request can be "

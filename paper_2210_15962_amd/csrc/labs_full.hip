@@ -392,7 +392,7 @@ __device__ __forceinline__ bool full_stop_requested(const uint32_t *flag) {
 // length too; kFLO the narrowest entry format of the lengths the kernel
 // runs; Codes its run codes; kSv the serving form: walks that pause and
 // resume across launches).
-template <int NW, int kFLO, class Codes, bool kSv = false>
+template <int NW, int kFLO, class Codes, bool kSv = false, bool kPrio = true>
 __device__ __forceinline__ void run_full_block(const FullTask &a, uint8_t *lds) {
   using Gm = Geom<NW>;
   constexpr int G = kG, K = kK, lgG = 2;
@@ -637,6 +637,7 @@ __device__ __forceinline__ void run_full_block(const FullTask &a, uint8_t *lds) 
     bool done = !active;
     uint32_t win = kKeyMax;
 
+    issue_priority<kPrioScanEarly, kPrio>();
     // (0) main scan, on as few planes as the wave's current c values allow.
 #pragma unroll
     for (int q = 0; q < K; ++q) tk[q] = kKeyMax;
@@ -650,6 +651,7 @@ __device__ __forceinline__ void run_full_block(const FullTask &a, uint8_t *lds) 
 #pragma unroll 1
     for (int sr = 0; sr < nruns; ++sr) {
       const uint32_t e0 = __builtin_amdgcn_readfirstlane(runs[sr]);
+      scan_run_priority<kPrio>(sr, nruns);
       const int ib = (int)(e0 >> 8);
       const int ie = (int)(__builtin_amdgcn_readfirstlane(runs[sr + 1]) >> 8);
       with_words<NW, Codes>((int)(e0 & 0xFFu), [&](auto Fc, auto Bc) __attribute__((always_inline)) {
@@ -670,6 +672,7 @@ __device__ __forceinline__ void run_full_block(const FullTask &a, uint8_t *lds) 
         else scan(std::integral_constant<int, 0>{});
       });
     }
+    issue_priority<kPrioResolve, kPrio>();
     // The predecessor is visited: drop it from its owner's top-K.
     if (prev_im1 != 0xFFFFFFFFu && (int)(prev_im1 % G) == r) {
       bool found = false;
@@ -745,7 +748,9 @@ __device__ __forceinline__ void run_full_block(const FullTask &a, uint8_t *lds) 
           pbucket = (pbucket + 1u == a.n_buckets) ? 0u : pbucket + 1u;
         }
       };
+      issue_priority<kPrioProbe, kPrio>();
       if (head_valid && hstat == 0 && eager) probe_head(head);
+      issue_priority<kPrioResolve, kPrio>();
       eager = false;
       // Every head already known to be visited leaves its list now (a visited
       // neighbour is never chosen), so the merge sees only heads that are new
@@ -767,7 +772,9 @@ __device__ __forceinline__ void run_full_block(const FullTask &a, uint8_t *lds) 
       const uint32_t gmin = group_min<G>(my);
       const bool owner = cur_valid && my == gmin;
       if (__ballot(owner && hstat == 0) != 0ull) {
+        issue_priority<kPrioProbe, kPrio>();
         if (owner && hstat == 0) probe_head(cur);
+        issue_priority<kPrioResolve, kPrio>();
       }
       const uint32_t ostat = group_max<G>(owner ? (uint32_t)(hstat + 1) : 0u);
       const bool exhausted_any = group_max<G>((!done && !lane_empty && npop >= K) ? 1u : 0u) != 0u;
@@ -797,6 +804,7 @@ __device__ __forceinline__ void run_full_block(const FullTask &a, uint8_t *lds) 
     }
 
     // ---- move ---------------------------------------------------------------
+    issue_priority<kPrioMove, kPrio>();
     if (active) {
       if (win == kKeyMax) {
         active = false;         // trapped walk stops here
@@ -954,7 +962,7 @@ __global__ void __launch_bounds__(kBlock, full_batch_occupancy(NHI, kSv)) full_b
     t.step_end = in.step_end;
     t.preempt = b.preempt;
     t.done_flag = b.item_done ? b.item_done + it : nullptr;
-    run_full_block<NHI, entry_format(NLO == 1 ? 3 : 32 * (NLO - 1) + 2), ClassCodes<NLO, NHI>, kSv>(t, lds);
+    run_full_block<NHI, entry_format(NLO == 1 ? 3 : 32 * (NLO - 1) + 2), ClassCodes<NLO, NHI>, kSv, kBatchPriority>(t, lds);
   }
 }
 

@@ -467,7 +467,7 @@ __device__ __forceinline__ bool stop_requested(const uint32_t *flag) {
 
 // kSv: the serving form of the batch kernel (per-walk status, walks that
 // resume at different move counts, the host stop flag, item completion).
-template <int NW, int G, int K, bool kSv = false>
+template <int NW, int G, int K, bool kSv = false, bool kPrio = true>
 __device__ __forceinline__ void run_block(const BlockTask &a, uint8_t *lds) {
   using Gm = Geom<NW>;
   const int Gl = (G > 0) ? G : a.lanes;        // lanes per walk (wave-uniform)
@@ -758,6 +758,7 @@ __device__ __forceinline__ void run_block(const BlockTask &a, uint8_t *lds) {
     bool done = !active;
     uint32_t win = kKeyMax;
 
+    issue_priority<kPrioScanEarly, kPrio>();
     // (0) main scan: every local candidate goes into the top-K, evaluated on
     //     as few C planes as the wave's current C values allow.
 #pragma unroll
@@ -770,6 +771,7 @@ __device__ __forceinline__ void run_block(const BlockTask &a, uint8_t *lds) {
 #pragma unroll 1
     for (int sr = 0; sr < nruns; ++sr) {
       const uint32_t e0 = __builtin_amdgcn_readfirstlane(runs[sr]);
+      scan_run_priority<kPrio>(sr, nruns);
       const int ib = (int)(e0 >> 8);
       const int ie = (int)(__builtin_amdgcn_readfirstlane(runs[sr + 1]) >> 8);
       with_words<NW, kMask>((int)(e0 & 0xFFu), [&](auto Fc, auto Bc) __attribute__((always_inline)) {
@@ -792,6 +794,7 @@ __device__ __forceinline__ void run_block(const BlockTask &a, uint8_t *lds) {
         else scan(std::integral_constant<int, 0>{});
       });
     }
+    issue_priority<kPrioResolve, kPrio>();
     // The predecessor is visited: drop it from its owner's top-K.
     if (prev_jm1 != 0xFFFFFFFFu && (int)(prev_jm1 % Gl) == r) {
       bool found = false;
@@ -886,7 +889,9 @@ __device__ __forceinline__ void run_block(const BlockTask &a, uint8_t *lds) {
         hstat = 0;
         pstarted = false;
       };
+      issue_priority<kPrioProbe, kPrio>();
       if (head_valid && hstat == 0 && eager) probe_head(head);
+      issue_priority<kPrioResolve, kPrio>();
       eager = false;
       // Every head already known to be visited leaves its list now (a visited
       // neighbour is never chosen), so the merge sees only heads that are new
@@ -900,7 +905,9 @@ __device__ __forceinline__ void run_block(const BlockTask &a, uint8_t *lds) {
       const uint32_t gmin = grp_min<G>(my, Gl);
       const bool owner = cur_valid && my == gmin;
       if (__ballot(owner && hstat == 0) != 0ull) {
+        issue_priority<kPrioProbe, kPrio>();
         if (owner && hstat == 0) probe_head(cur);
+        issue_priority<kPrioResolve, kPrio>();
       }
       const uint32_t ostat = grp_max<G>(owner ? (uint32_t)(hstat + 1) : 0u, Gl);
       const bool exhausted_any = grp_max<G>((!done && !lane_empty && npop >= K) ? 1u : 0u, Gl) != 0u;
@@ -922,6 +929,7 @@ __device__ __forceinline__ void run_block(const BlockTask &a, uint8_t *lds) {
     }
 
     // ---- move -------------------------------------------------------------
+    issue_priority<kPrioMove, kPrio>();
     if (active) {
       if (win == kKeyMax) {
         active = false;         // trapped walk stops here
@@ -1087,7 +1095,7 @@ __global__ void __launch_bounds__(kBlock, BatchOccupancy<NWMAX>::value) batch_ke
     // Compiled for the largest lag-word class of the batch: shorter lengths
     // skip the unused lag words (uniform guards), lanes per walk is a runtime
     // value, so one code path serves every item.
-    run_block<NWMAX, 0, 3, kSv>(t, lds);
+    run_block<NWMAX, 0, 3, kSv, kBatchPriority>(t, lds);
   }
 }
 
