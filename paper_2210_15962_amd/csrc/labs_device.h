@@ -73,13 +73,17 @@ __device__ __forceinline__ uint32_t funnel(uint32_t hi, uint32_t lo, uint32_t sh
 // step.  When several waves of a SIMD are ready, the higher priority issues
 // first; a wave is raised as its scan nears the end and while it issues a
 // visited-table probe, and lowered for the move, so a wave's HBM round trip
-// starts as early as possible and overlaps the other waves' scans.  Measured
-// at four waves per SIMD: 12-13 % more walk steps per second than issuing by
-// age alone (skew-symmetric L = 151, whole space L = 128), same results.
+// starts as early as possible and overlaps the other waves' scans.  Whether
+// that beats issuing by age depends on the kernel's shape, so it is used
+// where it measured faster (65,536 walks per length, with and without, on
+// one GPU): skew-symmetric walk kernels with 1, 2, 3 or 6 lag words (+3 to
+// +14 %; 4 and 5 words lost 4-5 %), whole-space walk kernels with 2, 3, 4,
+// 7 or 8 words (+3 to +14 %; 1, 5 and 6 words lost 3-5 %).  The persistent
+// batch kernels issue by age (the schedule measured 1-7 % slower there).
 enum : int { kPrioMove = 0, kPrioResolve = 1, kPrioScanEarly = 1, kPrioScanLate = 2, kPrioProbe = 3 };
-// The persistent batch kernels (two or three waves per SIMD) issue by age:
-// there the same schedule measured 1-7 % slower.
 constexpr bool kBatchPriority = false;
+constexpr bool walk_priority(int nw) { return nw <= 3 || nw == 6; }
+constexpr bool full_walk_priority(int nw) { return (nw >= 2 && nw <= 4) || nw >= 7; }
 
 template <int P, bool kOn>
 __device__ __forceinline__ void issue_priority() {

@@ -906,7 +906,7 @@ __global__ void __launch_bounds__(kBlock, FullOccupancy<NW>::value) full_walk_ke
   t.step_end = w.walk_len;
   t.preempt = nullptr;
   t.done_flag = nullptr;
-  run_full_block<NW, entry_format(32 * (NW - 1) + 2), ClassCodes<NW, NW>>(t, lds);
+  run_full_block<NW, entry_format(32 * (NW - 1) + 2), ClassCodes<NW, NW>, false, full_walk_priority(NW)>(t, lds);
 }
 
 // Persistent whole-space batch kernel: every workgroup takes (instance, block)

@@ -1037,7 +1037,7 @@ __global__ void __launch_bounds__(kBlock) walk_kernel(const WalkLaunch w) {
   t.step_end = w.walk_len;
   t.preempt = nullptr;
   t.done_flag = nullptr;
-  run_block<NW, G, K>(t, lds);
+  run_block<NW, G, K, false, walk_priority(NW)>(t, lds);
 }
 
 // ---------------------------------------------------------------------------
