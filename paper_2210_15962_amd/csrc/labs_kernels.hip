@@ -941,19 +941,25 @@ __device__ __forceinline__ void run_block(const BlockTask &a, uint8_t *lds) {
         CandVec<NW> cv;
         load_candidate<NW>(desc + jm1 * Gm::DESC, cols, colbase, cv, NW, Gm::NWB);
         apply_move_planes<NW>(cv, Pl);
-        // flip sequence positions j and L+1-j (same class) in all arrays
+        // flip sequence positions j and L+1-j (same class) in all arrays, as
+        // LDS xor without return (no read-modify-write round trips; each lane
+        // owns its column words)
         const int j = (int)jm1 + 1;
         const int c = j & 1, nc = c ? n1 : n0, af = c ? 0 : 1;
+        auto flip = [&](int word, int bit) {
+          __hip_atomic_fetch_xor(&colw[word * kBlock + tid], 1u << bit, __ATOMIC_RELAXED,
+                                 __HIP_MEMORY_SCOPE_WAVEFRONT);
+        };
         {
           const int rr = (j - 1) >> 1, rv = nc - 1 - rr;
-          colw[(af * Gm::NWA + (rr >> 5)) * kBlock + tid] ^= 1u << (rr & 31);
-          colw[((af + 2) * Gm::NWA + (rv >> 5)) * kBlock + tid] ^= 1u << (rv & 31);
+          flip(af * Gm::NWA + (rr >> 5), rr & 31);
+          flip((af + 2) * Gm::NWA + (rv >> 5), rv & 31);
         }
         if (j < D) {
           const int q = L + 1 - j;
           const int rr = (q - 1) >> 1, rv = nc - 1 - rr;
-          colw[(af * Gm::NWA + (rr >> 5)) * kBlock + tid] ^= 1u << (rr & 31);
-          colw[((af + 2) * Gm::NWA + (rv >> 5)) * kBlock + tid] ^= 1u << (rv & 31);
+          flip(af * Gm::NWA + (rr >> 5), rr & 31);
+          flip((af + 2) * Gm::NWA + (rv >> 5), rv & 31);
         }
         const Key NP = flip_key_n<KWM>(P, jm1);
         // the lane that probed the winner inserts it at the slot it found
