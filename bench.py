@@ -5,7 +5,7 @@ labs_walks over the headline workload (L = 151, 65,536 walks of 131,072 moves
 from seeded uniform starts).  Prints one JSON line with walk steps/s (Sum of
 steps_done over the timed steps / time), neighbour evaluations/s, the INT32
 VALU roofline of the walk kernel, the served stream (p50/p99 latency and
-served vs plain-batch steps/s at 10 and 200 req/s) and the CPU oracle baseline.
+served vs plain-batch steps/s at 10, 25 and 200 req/s) and the CPU oracle baseline.
 Other workloads run alone under their flags (--full, --full-batch, --paper-regime,
 --mixed-batch, --serve-sweep, --serve-full-sweep, --solve-target).
 
@@ -667,7 +667,7 @@ def main():
     del ws
     torch.cuda.empty_cache()
     if not args.no_serve:
-        # both ends of the 10-200 req/s range: near capacity, and saturated
+        # near capacity (10 req/s), just saturated (25) and far past it (200)
         batch = run_plain_batch(args.serve_requests, args.load_factor)
         out["serving"] = [run_serving(args.serve_requests, rate, args.load_factor, args.serve_chunk,
                                       batch=batch)
