@@ -299,8 +299,10 @@ int32_t labs_batch_graph_destroy(labs_batch_graph *graph);
  *     lanes_per_walk / load_factor are 0 (get returns LABS_ENOTFOUND if L has
  *     no entry, and the built-in default in the outputs).
  *   labs_autotune : times lanes_per_walk in {2, 4, 8} and load factors
- *     {0.5, 0.67} on a short run of n_walks x walk_len seeded walks, stores
- *     the fastest in the table and returns it.  n_walks should fill the GPU
+ *     {0.5, 0.67} on a short run of n_walks x walk_len seeded walks (one
+ *     instance through labs_walks_batch, i.e. on the batch kernel that runs
+ *     batches and served requests), stores the fastest in the table and
+ *     returns it.  n_walks should fill the GPU
  *     at 2 lanes per walk (about 131,072 walks on 256 CUs), else the timing
  *     measures fill rather than cost per step.  The workspace must hold
  *     labs_walks_workspace_bytes(L, n_walks, walk_len, lanes 2, load factor

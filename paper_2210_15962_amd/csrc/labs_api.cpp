@@ -855,13 +855,23 @@ int32_t labs_autotune(int32_t L, int64_t n_walks, int64_t walk_len, void *worksp
   const double lfs[2] = {0.5, 0.67};
   for (int li = 0; li < 3 && e == hipSuccess; ++li) {
     for (int fi = 0; fi < 2 && e == hipSuccess; ++fi) {
-      labs_plan p{lanes[li], lfs[fi], 0};
-      labs_walk_out o{best_seq, best_E, steps, nullptr, nullptr, nullptr, 0};
+      // Timed on the persistent batch kernel (one instance), which runs the
+      // batches and served requests the table is for; the batch uses as many
+      // resident workgroups as the workspace has table slices for.
+      labs_instance in{};
+      in.L = L;
+      in.lanes_per_walk = lanes[li];
+      in.n_walks = n_walks;
+      in.walk_len = walk_len;
+      in.starts = nullptr;
+      in.load_factor = lfs[fi];
+      in.out = labs_walk_out{best_seq, best_E, steps, nullptr, nullptr, nullptr, 0};
       // one untimed run (clock ramp), one timed run
       for (int rep = 0; rep < 2 && e == hipSuccess; ++rep) {
+        in.seed = 1234 + rep;
         if (rep == 1) e = hipEventRecord(t0, st);
         if (e != hipSuccess) break;
-        rc = labs_walks(nullptr, L, n_walks, walk_len, 1234 + rep, &o, tables, tables_bytes, &p, stream);
+        rc = labs_walks_batch(&in, 1, tables, tables_bytes, stream);
         if (rc != LABS_OK) { e = hipErrorUnknown; break; }
         if (rep == 1) e = hipEventRecord(t1, st);
       }
